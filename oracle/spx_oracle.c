@@ -1,0 +1,576 @@
+/*
+ * CPU oracle for the multiresolution simplex hash encoding
+ * (Wen & Yang, "Efficient Encoding of Graphics Primitives with
+ * Simplex-based Structures", arXiv 2311.15439).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain statement of what
+ * the GPU path must compute.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header,
+ * constant table or helper with the HIP library: every constant below is
+ * derived here from its definition.
+ *
+ * Precision policy
+ *   - Where floating point decides an integer (which lattice cell, which of
+ *     the n! simplices, which hash slot) the decision is taken in IEEE
+ *     binary32, in a fixed operation order, with no contraction (build with
+ *     -ffp-contract=off).  This is the kernel's precision; the paper fixes
+ *     none.
+ *   - Everything else (barycentric weights, interpolation, adjoint sums,
+ *     the MLP) is evaluated in binary64 from the exact binary32 inputs.
+ *   - A binary32 mirror of the weights (the same subtractions in float) is
+ *     also produced so that the GPU's weights can be compared bit for bit.
+ *
+ * Parity pins (what fixes each function independently of this file) live in
+ * tests/test_oracle_pins.py.  MLP and Adam rows: pinned against numpy and
+ * closed-form special cases; nothing here is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_DIM 6
+#define ORC_MAX_LEVELS 32
+#define ORC_SIMPLEX 0
+#define ORC_GRID 1
+#define ORC_F32 0
+#define ORC_F16 1
+
+/* ------------------------------------------------------------------------ */
+/* Constants.                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Skew factor of Eq. 2 (Sec. 2.2(a)): F_n = (sqrt(n+1) - 1) / n. */
+double orc_skew_factor(int n) { return (sqrt((double)n + 1.0) - 1.0) / (double)n; }
+
+/* Unskew factor of Eq. 3 (Sec. 2.2(d)): G_n = (1 - 1/sqrt(n+1)) / n. */
+double orc_unskew_factor(int n) { return (1.0 - 1.0 / sqrt((double)n + 1.0)) / (double)n; }
+
+/* Adjustment scale of Sec. 5.1: S_n = sqrt(n+1), the image of the unit
+ * cube's far corner along each axis after the skew. */
+double orc_adjust_scale(int n) { return sqrt((double)n + 1.0); }
+
+/* Equal-memory level multiplier of Sec. 5.2: (n+1)^((n-1)/(2n)).  The paper
+ * scales each level by it when it compares against the grid at a fixed table
+ * size. */
+double orc_equal_memory_factor(int n) {
+    return pow((double)n + 1.0, (double)(n - 1) / (2.0 * (double)n));
+}
+
+/* Geometric level schedule N_l = floor(N_min * b^l + 1e-6).  The paper only
+ * says the cube is divided "accordingly to each level" (Sec. 5.1); the
+ * geometric progression and the 1e-6 guard (so that the top level of a
+ * schedule given by its two ends lands on the integer end) are this build's
+ * reading. */
+void orc_level_resolutions(double n_min, double growth, int L, int32_t* res_out) {
+    for (int l = 0; l < L; ++l) res_out[l] = (int32_t)floor(n_min * pow(growth, (double)l) + 1e-6);
+}
+
+/* Per-level multiplier applied to the skewed coordinate (Sec. 5.1): the
+ * skewed unit cube spans [0, S_n]^n, so dividing by S_n brings it back to
+ * [0,1]^n before the level resolution N_l (times the optional equal-memory
+ * factor) is applied.  Rounded to binary32 once.  The grid baseline uses N_l
+ * directly (no skew). */
+void orc_level_scales(int n, int L, const int32_t* res, int cell, int equal_memory, float* sigma_out) {
+    double cn = equal_memory ? orc_equal_memory_factor(n) : 1.0;
+    for (int l = 0; l < L; ++l) {
+        if (cell == ORC_GRID)
+            sigma_out[l] = (float)((double)res[l] * cn);
+        else
+            sigma_out[l] = (float)(((double)res[l] * cn) / orc_adjust_scale(n));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spatial hash.  The paper defers to the multiresolution hash encoding it   */
+/* builds on and prints no function.  Reading: h(v) = XOR_i (u32(v_i)*P_i)  */
+/* mod 2^32, masked to the table size, with P_0 = 1, P_1 = 2654435761, and  */
+/* P_2..P_5 the smallest primes not below floor(2^32 * frac(sqrt(q))) for   */
+/* q = 2, 3, 5, 7.  The primes are derived here at run time.                */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t isqrt_u128(unsigned __int128 a) {
+    /* floor(sqrt(a)) by bisection on 64-bit candidates. */
+    uint64_t lo = 0, hi = UINT64_MAX;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2 + 1;
+        unsigned __int128 sq = (unsigned __int128)mid * mid;
+        if (sq <= a) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+static int is_prime_u64(uint64_t v) {
+    if (v < 2) return 0;
+    if (v % 2 == 0) return v == 2;
+    for (uint64_t d = 3; d * d <= v; d += 2)
+        if (v % d == 0) return 0;
+    return 1;
+}
+
+void orc_hash_primes(uint32_t* P /* [ORC_MAX_DIM] */) {
+    static const uint32_t q[4] = {2, 3, 5, 7};
+    P[0] = 1u;
+    P[1] = 2654435761u;
+    for (int k = 0; k < 4; ++k) {
+        /* floor(sqrt(q) * 2^32) = isqrt(q * 2^64); drop the integer part. */
+        unsigned __int128 a = (unsigned __int128)q[k] << 64;
+        uint64_t r = isqrt_u128(a);
+        uint64_t frac = r - ((uint64_t)isqrt_u128((unsigned __int128)q[k]) << 32);
+        while (!is_prime_u64(frac)) ++frac;
+        P[2 + k] = (uint32_t)frac;
+    }
+}
+
+/* The multipliers are derived once when the library is loaded. */
+static uint32_t g_primes[ORC_MAX_DIM];
+__attribute__((constructor)) static void init_primes(void) { orc_hash_primes(g_primes); }
+
+uint32_t orc_hash(const int32_t* v, int n, int log2_T) {
+    uint32_t h = 0;
+    for (int i = 0; i < n; ++i) h ^= (uint32_t)v[i] * g_primes[i];
+    return h & ((1u << log2_T) - 1u);
+}
+
+/* ------------------------------------------------------------------------ */
+/* binary16 <-> binary64, written from the IEEE 754 binary16 format          */
+/* (1 sign bit, 5 exponent bits with bias 15, 10 fraction bits).             */
+/* ------------------------------------------------------------------------ */
+
+double orc_f16_to_f64(uint16_t h) {
+    int s = (h >> 15) & 1, e = (h >> 10) & 31, m = h & 1023;
+    double v;
+    if (e == 0) v = ldexp((double)m, -24);
+    else if (e == 31) v = m ? NAN : INFINITY;
+    else v = ldexp((double)(m + 1024), e - 25);
+    return s ? -v : v;
+}
+
+/* Round to nearest, ties to even. */
+uint16_t orc_f64_to_f16(double x) {
+    uint16_t sign = (signbit(x) ? 0x8000u : 0u);
+    double a = fabs(x);
+    if (isnan(x)) return 0x7e00u;
+    if (a >= 65520.0) return sign | 0x7c00u; /* beyond the last rounding boundary */
+    if (a < ldexp(1.0, -14)) {
+        double q = nearbyint(a * ldexp(1.0, 24)); /* subnormal: units of 2^-24 */
+        return sign | (uint16_t)q;               /* q == 1024 is the smallest normal */
+    }
+    int E;
+    frexp(a, &E);               /* a = m * 2^E, m in [0.5, 1) */
+    int e = E - 1;              /* a in [2^e, 2^(e+1)) */
+    double q = nearbyint(ldexp(a, 10 - e)); /* 11-bit significand in [1024, 2048] */
+    if (q == 2048.0) { q = 1024.0; e += 1; }
+    if (e > 15) return sign | 0x7c00u;
+    return sign | (uint16_t)(((e + 15) << 10) | ((int)q - 1024));
+}
+
+/* bfloat16: 8 exponent bits, 7 fraction bits; round to nearest even. */
+double orc_round_bf16(double x) {
+    if (x == 0.0 || isnan(x) || isinf(x)) return x;
+    int E;
+    frexp(fabs(x), &E);
+    int e = E - 1;
+    if (e < -126) e = -126; /* subnormal range keeps a fixed quantum */
+    double q = nearbyint(ldexp(x, 7 - e));
+    return ldexp(q, e - 7);
+}
+
+static double table_value(const void* tables, int dtype, size_t idx) {
+    if (dtype == ORC_F16) return orc_f16_to_f64(((const uint16_t*)tables)[idx]);
+    return (double)((const float*)tables)[idx];
+}
+
+/* ------------------------------------------------------------------------ */
+/* One level's lookup for one point.                                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n_dims, n_levels, log2_T, n_feat, table_dtype, cell;
+    int32_t res[ORC_MAX_LEVELS];
+    int equal_memory;
+} orc_encoding;
+
+/* Skewed coordinate of Eq. 2 in binary32: the coordinate sum is formed left
+ * to right, multiplied by F_n, and added to each coordinate. */
+static void skew_point_f32(int n, const float* x, float* y) {
+    float Fn = (float)orc_skew_factor(n);
+    float s = x[0];
+    for (int i = 1; i < n; ++i) s = s + x[i];
+    float t = s * Fn;
+    for (int i = 0; i < n; ++i) y[i] = x[i] + t;
+}
+
+/*
+ * Simplex lookup at one level (Secs. 4.2, 4.3 and 5.1).
+ *   p = sigma * y (binary32), cell corner c = floor(p), fractional part
+ *   f = p - c.  The fractional parts are ordered largest first by a stable
+ *   bubble sort (equal values keep axis order), which names the simplex of
+ *   the Kuhn subdivision containing p (Remark 2).  The walk starts at c and
+ *   adds one along the axis of each next-largest fraction, giving the n+1
+ *   vertices; the barycentric weights are 1 - f(1), f(1) - f(2), ...,
+ *   f(n-1) - f(n), f(n) over the sorted fractions (Sec. 4.3).
+ */
+static int simplex_lookup(int n, const float* y, float sigma, int32_t verts[][ORC_MAX_DIM],
+                          double* w64, float* w32, float* p_out) {
+    float p[ORC_MAX_DIM], f[ORC_MAX_DIM];
+    int32_t c[ORC_MAX_DIM];
+    int axis[ORC_MAX_DIM];
+    for (int i = 0; i < n; ++i) {
+        p[i] = y[i] * sigma;
+        c[i] = (int32_t)floorf(p[i]);
+        f[i] = p[i] - (float)c[i];
+        axis[i] = i;
+        if (p_out) p_out[i] = p[i];
+    }
+    /* bubble sort, descending, strict comparison => stable */
+    for (int pass = 0; pass < n - 1; ++pass)
+        for (int j = 0; j < n - 1 - pass; ++j)
+            if (f[axis[j]] < f[axis[j + 1]]) {
+                int t = axis[j]; axis[j] = axis[j + 1]; axis[j + 1] = t;
+            }
+    for (int i = 0; i < n; ++i) verts[0][i] = c[i];
+    for (int k = 1; k <= n; ++k) {
+        for (int i = 0; i < n; ++i) verts[k][i] = verts[k - 1][i];
+        verts[k][axis[k - 1]] += 1;
+    }
+    /* weights over the sorted fractions */
+    w64[0] = 1.0 - (double)f[axis[0]];
+    w32[0] = 1.0f - f[axis[0]];
+    for (int k = 1; k < n; ++k) {
+        w64[k] = (double)f[axis[k - 1]] - (double)f[axis[k]];
+        w32[k] = f[axis[k - 1]] - f[axis[k]];
+    }
+    w64[n] = (double)f[axis[n - 1]];
+    w32[n] = f[axis[n - 1]];
+    return n + 1;
+}
+
+/*
+ * 2^n-corner grid lookup (the baseline of Sec. 2.1 / Alg. 1): p = N_l * x,
+ * corners c + b for b in {0,1}^n enumerated in binary order (bit i is axis
+ * i), n-linear weights prod_i (b_i ? f_i : 1 - f_i).
+ */
+static int grid_lookup(int n, const float* x, float sigma, int32_t verts[][ORC_MAX_DIM],
+                       double* w64, float* w32, float* p_out) {
+    float p[ORC_MAX_DIM], f[ORC_MAX_DIM];
+    int32_t c[ORC_MAX_DIM];
+    for (int i = 0; i < n; ++i) {
+        p[i] = x[i] * sigma;
+        c[i] = (int32_t)floorf(p[i]);
+        f[i] = p[i] - (float)c[i];
+        if (p_out) p_out[i] = p[i];
+    }
+    int V = 1 << n;
+    for (int b = 0; b < V; ++b) {
+        double w = 1.0;
+        float wf = 1.0f;
+        for (int i = 0; i < n; ++i) {
+            int bit = (b >> i) & 1;
+            verts[b][i] = c[i] + bit;
+            w *= bit ? (double)f[i] : 1.0 - (double)f[i];
+            wf *= bit ? f[i] : 1.0f - f[i];
+        }
+        w64[b] = w;
+        w32[b] = wf;
+    }
+    return V;
+}
+
+static int lookup(const orc_encoding* e, const float* x, const float* y, float sigma,
+                  int32_t verts[][ORC_MAX_DIM], double* w64, float* w32, float* p_out) {
+    if (e->cell == ORC_GRID) return grid_lookup(e->n_dims, x, sigma, verts, w64, w32, p_out);
+    return simplex_lookup(e->n_dims, y, sigma, verts, w64, w32, p_out);
+}
+
+static int n_vertices(const orc_encoding* e) {
+    return e->cell == ORC_GRID ? (1 << e->n_dims) : e->n_dims + 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public entry points.                                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Debug view of the lookup: for each point and level, the n+1 (or 2^n)
+ * vertex coordinates, their hash slots, the binary64 and binary32 weights,
+ * and the scaled point p.  Any output pointer may be NULL.
+ * Shapes: verts [N,L,V,n] int32; idx [N,L,V] uint32; w64 [N,L,V];
+ * w32 [N,L,V]; p [N,L,n] float.
+ */
+void orc_encode_debug(const orc_encoding* e, int64_t N, const float* pts, int32_t* verts_out,
+                      uint32_t* idx_out, double* w64_out, float* w32_out, float* p_out) {
+    int n = e->n_dims, L = e->n_levels, V = n_vertices(e);
+    float sigma[ORC_MAX_LEVELS];
+    orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
+#pragma omp parallel for schedule(static)
+    for (int64_t pt = 0; pt < N; ++pt) {
+        const float* x = pts + pt * n;
+        float y[ORC_MAX_DIM];
+        skew_point_f32(n, x, y);
+        for (int l = 0; l < L; ++l) {
+            int32_t verts[1 << ORC_MAX_DIM][ORC_MAX_DIM];
+            double w64[1 << ORC_MAX_DIM];
+            float w32[1 << ORC_MAX_DIM], p[ORC_MAX_DIM];
+            lookup(e, x, y, sigma[l], verts, w64, w32, p);
+            size_t base = ((size_t)pt * L + l) * V;
+            for (int k = 0; k < V; ++k) {
+                if (verts_out)
+                    for (int i = 0; i < n; ++i) verts_out[(base + k) * n + i] = verts[k][i];
+                if (idx_out) idx_out[base + k] = orc_hash(verts[k], n, e->log2_T);
+                if (w64_out) w64_out[base + k] = w64[k];
+                if (w32_out) w32_out[base + k] = w32[k];
+            }
+            if (p_out)
+                for (int i = 0; i < n; ++i) p_out[((size_t)pt * L + l) * n + i] = p[i];
+        }
+    }
+}
+
+/*
+ * Forward encoding (Sec. 5 steps (a)-(d)): for every level, hash the
+ * vertices, look up their feature vectors in that level's table, take the
+ * barycentric-weighted sum, and concatenate the levels.
+ * tables: [L, 2^log2_T, F] in binary32 or binary16; out: [N, L*F] binary64.
+ */
+void orc_encode_fwd(const orc_encoding* e, int64_t N, const float* pts, const void* tables, double* out) {
+    int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
+    size_t T = (size_t)1 << e->log2_T;
+    float sigma[ORC_MAX_LEVELS];
+    orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
+#pragma omp parallel for schedule(static)
+    for (int64_t pt = 0; pt < N; ++pt) {
+        const float* x = pts + pt * n;
+        float y[ORC_MAX_DIM];
+        skew_point_f32(n, x, y);
+        for (int l = 0; l < L; ++l) {
+            int32_t verts[1 << ORC_MAX_DIM][ORC_MAX_DIM];
+            double w64[1 << ORC_MAX_DIM];
+            float w32[1 << ORC_MAX_DIM];
+            lookup(e, x, y, sigma[l], verts, w64, w32, NULL);
+            for (int j = 0; j < F; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < V; ++k) {
+                    uint32_t h = orc_hash(verts[k], n, e->log2_T);
+                    acc += w64[k] * table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j);
+                }
+                out[(size_t)pt * L * F + (size_t)l * F + j] = acc;
+            }
+        }
+    }
+}
+
+/*
+ * Magnitude companion of the forward pass: sum_k |w_k * t_k| per output.
+ * Used to state the forward error relative to the size of the terms.
+ */
+void orc_encode_fwd_absmag(const orc_encoding* e, int64_t N, const float* pts, const void* tables,
+                           double* out) {
+    int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
+    size_t T = (size_t)1 << e->log2_T;
+    float sigma[ORC_MAX_LEVELS];
+    orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
+#pragma omp parallel for schedule(static)
+    for (int64_t pt = 0; pt < N; ++pt) {
+        const float* x = pts + pt * n;
+        float y[ORC_MAX_DIM];
+        skew_point_f32(n, x, y);
+        for (int l = 0; l < L; ++l) {
+            int32_t verts[1 << ORC_MAX_DIM][ORC_MAX_DIM];
+            double w64[1 << ORC_MAX_DIM];
+            float w32[1 << ORC_MAX_DIM];
+            lookup(e, x, y, sigma[l], verts, w64, w32, NULL);
+            for (int j = 0; j < F; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < V; ++k) {
+                    uint32_t h = orc_hash(verts[k], n, e->log2_T);
+                    acc += fabs(w64[k] * table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j));
+                }
+                out[(size_t)pt * L * F + (size_t)l * F + j] = acc;
+            }
+        }
+    }
+}
+
+/*
+ * Adjoint of the forward encoding (Sec. 5 step (e)): the gradient of each
+ * output is accumulated into the looked-up feature vectors with the same
+ * barycentric weights.  d_out: [N, L*F] binary64; d_tables: [L, T, F]
+ * binary64, accumulated (+=).  Serial on purpose: the summation order is the
+ * plain point order.  If absmag is non-NULL it receives sum |w * d_out| per
+ * slot (same shape as d_tables, accumulated) and count the number of
+ * contributions per slot.
+ */
+void orc_encode_bwd(const orc_encoding* e, int64_t N, const float* pts, const double* d_out,
+                    double* d_tables, double* absmag, int64_t* count) {
+    int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
+    size_t T = (size_t)1 << e->log2_T;
+    float sigma[ORC_MAX_LEVELS];
+    orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
+    for (int64_t pt = 0; pt < N; ++pt) {
+        const float* x = pts + pt * n;
+        float y[ORC_MAX_DIM];
+        skew_point_f32(n, x, y);
+        for (int l = 0; l < L; ++l) {
+            int32_t verts[1 << ORC_MAX_DIM][ORC_MAX_DIM];
+            double w64[1 << ORC_MAX_DIM];
+            float w32[1 << ORC_MAX_DIM];
+            lookup(e, x, y, sigma[l], verts, w64, w32, NULL);
+            for (int k = 0; k < V; ++k) {
+                uint32_t h = orc_hash(verts[k], n, e->log2_T);
+                for (int j = 0; j < F; ++j) {
+                    size_t slot = ((size_t)l * T + h) * F + j;
+                    double g = d_out[(size_t)pt * L * F + (size_t)l * F + j];
+                    d_tables[slot] += w64[k] * g;
+                    if (absmag) absmag[slot] += fabs(w64[k] * g);
+                    if (count) count[slot] += 1;
+                }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tiny fully connected network (Sec. 5 step (e); about 7k parameters):     */
+/* in -> H -> H -> out with ReLU on the hidden layers and a linear output.  */
+/* Weights are binary16, row-major W[out][in].  The input and each hidden   */
+/* activation are rounded to binary16 where the kernel stores them in that  */
+/* format; every product and sum is binary64.                               */
+/* ------------------------------------------------------------------------ */
+
+static double f16r(double v) { return orc_f16_to_f64(orc_f64_to_f16(v)); }
+
+/* out [N, d_out] binary64.  If absmag != NULL it receives the same forward
+ * pass over |W| and |x| without the ReLU (an upper bound on every partial
+ * sum's size, used for error statements). */
+void orc_mlp_fwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const uint16_t* W1,
+                 const uint16_t* W2, const uint16_t* W3, double* out, double* absmag) {
+#pragma omp parallel for schedule(static)
+    for (int64_t pt = 0; pt < N; ++pt) {
+        double xin[256], h1[256], h2[256], a1[256], a2[256];
+        for (int i = 0; i < d_in; ++i) xin[i] = orc_f16_to_f64(x[pt * d_in + i]);
+        for (int o = 0; o < H; ++o) {
+            double s = 0.0, sa = 0.0;
+            for (int i = 0; i < d_in; ++i) {
+                double w = orc_f16_to_f64(W1[o * d_in + i]);
+                s += w * xin[i];
+                sa += fabs(w) * fabs(xin[i]);
+            }
+            h1[o] = f16r(s > 0.0 ? s : 0.0);
+            a1[o] = sa;
+        }
+        for (int o = 0; o < H; ++o) {
+            double s = 0.0, sa = 0.0;
+            for (int i = 0; i < H; ++i) {
+                double w = orc_f16_to_f64(W2[o * H + i]);
+                s += w * h1[i];
+                sa += fabs(w) * a1[i];
+            }
+            h2[o] = f16r(s > 0.0 ? s : 0.0);
+            a2[o] = sa;
+        }
+        for (int o = 0; o < d_out; ++o) {
+            double s = 0.0, sa = 0.0;
+            for (int i = 0; i < H; ++i) {
+                double w = orc_f16_to_f64(W3[o * H + i]);
+                s += w * h2[i];
+                sa += fabs(w) * a2[i];
+            }
+            out[pt * d_out + o] = s;
+            if (absmag) absmag[pt * d_out + o] = sa;
+        }
+    }
+}
+
+/*
+ * Backward pass of the network.  The forward pass is recomputed as above.
+ * Gradient operands are rounded to bfloat16 where the kernel feeds them to
+ * its matrix unit: the incoming output gradient, the weights in the
+ * transposed products, the activations in the weight-gradient products, and
+ * each masked hidden gradient.  The ReLU mask is taken on the stored
+ * (binary16) activation.
+ *   d_y   [N, d_out] binary32 (gradient of the loss w.r.t. the output)
+ *   d_x   [N, d_in] binary64 (written)
+ *   dW1 [H, d_in], dW2 [H, H], dW3 [d_out, H] binary64 (written)
+ *   margin [N] (optional): smallest |pre-activation| of the point, so a test
+ *   can tell which points sit on a ReLU kink.
+ */
+void orc_mlp_bwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const uint16_t* W1,
+                 const uint16_t* W2, const uint16_t* W3, const float* d_y, double* d_x, double* dW1,
+                 double* dW2, double* dW3, double* margin) {
+    memset(dW1, 0, sizeof(double) * H * d_in);
+    memset(dW2, 0, sizeof(double) * H * H);
+    memset(dW3, 0, sizeof(double) * d_out * H);
+    for (int64_t pt = 0; pt < N; ++pt) {
+        double xin[256], h1[256], h2[256], dy[256], dh2[256], dh1[256];
+        double mg = INFINITY;
+        for (int i = 0; i < d_in; ++i) xin[i] = orc_f16_to_f64(x[pt * d_in + i]);
+        for (int o = 0; o < H; ++o) {
+            double s = 0.0;
+            for (int i = 0; i < d_in; ++i) s += orc_f16_to_f64(W1[o * d_in + i]) * xin[i];
+            h1[o] = f16r(s > 0.0 ? s : 0.0);
+            if (fabs(s) < mg) mg = fabs(s);
+        }
+        for (int o = 0; o < H; ++o) {
+            double s = 0.0;
+            for (int i = 0; i < H; ++i) s += orc_f16_to_f64(W2[o * H + i]) * h1[i];
+            h2[o] = f16r(s > 0.0 ? s : 0.0);
+            if (fabs(s) < mg) mg = fabs(s);
+        }
+        if (margin) margin[pt] = mg;
+        for (int o = 0; o < d_out; ++o) dy[o] = orc_round_bf16((double)d_y[pt * d_out + o]);
+        /* layer 3: dW3 += dy h2^T ; dh2 = W3^T dy, masked */
+        for (int o = 0; o < d_out; ++o)
+            for (int i = 0; i < H; ++i) dW3[o * H + i] += dy[o] * orc_round_bf16(h2[i]);
+        for (int i = 0; i < H; ++i) {
+            double s = 0.0;
+            for (int o = 0; o < d_out; ++o) s += orc_round_bf16(orc_f16_to_f64(W3[o * H + i])) * dy[o];
+            dh2[i] = orc_round_bf16(h2[i] > 0.0 ? s : 0.0);
+        }
+        /* layer 2 */
+        for (int o = 0; o < H; ++o)
+            for (int i = 0; i < H; ++i) dW2[o * H + i] += dh2[o] * orc_round_bf16(h1[i]);
+        for (int i = 0; i < H; ++i) {
+            double s = 0.0;
+            for (int o = 0; o < H; ++o) s += orc_round_bf16(orc_f16_to_f64(W2[o * H + i])) * dh2[o];
+            dh1[i] = orc_round_bf16(h1[i] > 0.0 ? s : 0.0);
+        }
+        /* layer 1 */
+        for (int o = 0; o < H; ++o)
+            for (int i = 0; i < d_in; ++i) dW1[o * d_in + i] += dh1[o] * orc_round_bf16(xin[i]);
+        for (int i = 0; i < d_in; ++i) {
+            double s = 0.0;
+            for (int o = 0; o < H; ++o) s += orc_round_bf16(orc_f16_to_f64(W1[o * d_in + i])) * dh1[o];
+            d_x[pt * d_in + i] = s;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Optimizer step for the tables (the paper trains by gradient descent and  */
+/* states no optimizer; Adam, Kingma & Ba 2015, Algorithm 1, is this        */
+/* build's choice).  Binary64 arithmetic on binary32 state; the binary16    */
+/* copy is the round-to-nearest-even image of the updated parameter.        */
+/* step is the 1-based iteration count t.                                  */
+/* ------------------------------------------------------------------------ */
+void orc_adam_step(int64_t n, float* param, const float* grad, float* m, float* v, double lr,
+                   double beta1, double beta2, double eps, int64_t step, uint16_t* param_f16) {
+    double bc1 = 1.0 - pow(beta1, (double)step);
+    double bc2 = 1.0 - pow(beta2, (double)step);
+    for (int64_t i = 0; i < n; ++i) {
+        double g = grad[i];
+        double mi = beta1 * m[i] + (1.0 - beta1) * g;
+        double vi = beta2 * v[i] + (1.0 - beta2) * g * g;
+        double mhat = mi / bc1, vhat = vi / bc2;
+        double p = (double)param[i] - lr * mhat / (sqrt(vhat) + eps);
+        m[i] = (float)mi;
+        v[i] = (float)vi;
+        param[i] = (float)p;
+        if (param_f16) param_f16[i] = orc_f64_to_f16((double)param[i]);
+    }
+}
+
+/* Round-to-nearest-even binary32 -> binary16 copy. */
+void orc_cast_f32_f16(int64_t n, const float* src, uint16_t* dst) {
+    for (int64_t i = 0; i < n; ++i) dst[i] = orc_f64_to_f16((double)src[i]);
+}

@@ -1,0 +1,59 @@
+"""Planted mistakes: each mutant of the oracle (a dropped term, a wrong sign,
+a wrong index, a transposed operand, a wrong constant) must fail the pin
+suite.  Built and run on the CPU only."""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "spx_oracle.c")
+
+MUTANTS = {
+    "skew sign": ("y[i] = x[i] + t;", "y[i] = x[i] - t;"),
+    "skew factor": ("return (sqrt((double)n + 1.0) - 1.0) / (double)n;",
+                    "return (sqrt((double)n + 1.0) - 1.0) / (double)(n + 1);"),
+    "scale direction": ("/ orc_adjust_scale(n));", "* orc_adjust_scale(n));"),
+    "sort order": ("if (f[axis[j]] < f[axis[j + 1]])", "if (f[axis[j]] > f[axis[j + 1]])"),
+    "tie rule": ("if (f[axis[j]] < f[axis[j + 1]])", "if (f[axis[j]] <= f[axis[j + 1]])"),
+    "first weight": ("w64[0] = 1.0 - (double)f[axis[0]];", "w64[0] = 1.0 - (double)f[axis[n - 1]];"),
+    "last weight": ("w64[n] = (double)f[axis[n - 1]];", "w64[n] = (double)f[axis[0]];"),
+    "walk axis": ("verts[k][axis[k - 1]] += 1;", "verts[k][axis[n - k]] += 1;"),
+    "hash prime": ("P[1] = 2654435761u;", "P[1] = 2654435769u;"),
+    "hash op": ("h ^= (uint32_t)v[i] * g_primes[i];", "h += (uint32_t)v[i] * g_primes[i];"),
+    "adjoint weight": ("d_tables[slot] += w64[k] * g;", "d_tables[slot] += g;"),
+    "grid weight": ("w *= bit ? (double)f[i] : 1.0 - (double)f[i];",
+                    "w *= bit ? 1.0 - (double)f[i] : (double)f[i];"),
+    "mlp transposed": ("s += w * h1[i];", "s += orc_f16_to_f64(W2[i * H + o]) * h1[i];"),
+    "mlp relu dropped": ("h2[o] = f16r(s > 0.0 ? s : 0.0);\n            a2[o] = sa;",
+                         "h2[o] = f16r(s);\n            a2[o] = sa;"),
+    "mlp bwd mask": ("dh1[i] = orc_round_bf16(h1[i] > 0.0 ? s : 0.0);", "dh1[i] = orc_round_bf16(s);"),
+    "f16 rounding": ("double q = nearbyint(ldexp(a, 10 - e));", "double q = floor(ldexp(a, 10 - e));"),
+    "adam bias correction": ("double mhat = mi / bc1, vhat = vi / bc2;", "double mhat = mi, vhat = vi / bc2;"),
+}
+
+
+def _run_mutant(name, old, new, tmp):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, name
+    path = os.path.join(tmp, name.replace(" ", "_") + ".c")
+    lib = path[:-2] + ".so"
+    open(path, "w").write(src.replace(old, new, 1))
+    subprocess.run(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", lib, path, "-lm"], check=True)
+    env = dict(os.environ, SPX_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+def test_every_planted_mistake_fails_a_pin():
+    with tempfile.TemporaryDirectory() as tmp:
+        with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
+            results = list(ex.map(lambda kv: _run_mutant(kv[0], *kv[1], tmp), MUTANTS.items()))
+    survivors = [name for name, rc in results if rc == 0]
+    assert not survivors, f"mutants not caught by the pins: {survivors}"
