@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Benchmark: one training step of the multiresolution simplex hash encoding
+on the image-fitting workload (n=2, L=16, T=2^22, F=2 binary16 tables,
+resolutions 16..32768, 2^20 random pixel positions of a 16384^2 image per
+step, MLP 32->64->64->3).
+
+A step is the whole hot path on one batch already resident in GPU memory:
+  encode forward -> MLP forward -> L2 loss gradient -> MLP backward ->
+  encode adjoint -> Adam on the tables (binary32 master + binary16 copy,
+  gradient cleared) -> Adam on the MLP weights.
+Prints one JSON line.  The same step with the 2^n-corner grid baseline, the
+encoding kernels alone (simplex and grid), and the CPU oracle on a bounded
+sample are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def _workload(name):
+    from paper_2311_15439_amd import inputs
+    return {"image-2d": inputs.IMAGE_2D, "volume-3d": inputs.VOLUME_3D}[name]
+
+
+def _points(w, batch):
+    from paper_2311_15439_amd import inputs
+    if w.name.startswith("image"):
+        return inputs.pixel_points(w.n_points, w.seed_points + 1000 * batch)
+    return inputs.ray_points(w.n_points // 256, 256, w.seed_points + 1000 * batch)
+
+
+def _targets(w, pts, batch):
+    from paper_2311_15439_amd import inputs
+    if w.name.startswith("image"):
+        return inputs.procedural_rgb(pts, 4)
+    return inputs.procedural_density(pts, 7)
+
+
+class TrainStep:
+    """All device buffers of one training step; launches only library kernels."""
+
+    def __init__(self, w, cell, batches, host_tables, weights, d_out):
+        import torch
+        from paper_2311_15439_amd import spx
+        self.torch, self.spx = torch, spx
+        dev = "cuda"
+        self.w = w
+        self.res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
+        self.enc = spx.Encoding(w.n_dims, self.res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16, cell=cell)
+        self.N = w.n_points
+        self.batches = [(torch.from_numpy(p).to(dev), torch.from_numpy(t).to(dev)) for p, t in batches]
+        self.master = torch.from_numpy(host_tables.astype(np.float32)).to(dev)
+        self.tab16 = torch.from_numpy(host_tables.astype(np.float16)).to(dev)
+        self.grad = torch.zeros_like(self.master)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        D = w.n_levels * w.n_feat
+        self.d_out = d_out
+        self.mlp = spx.make_mlp(D, 64, d_out)
+        W1, W2, W3 = weights
+        sizes = [W1.size, W2.size, W3.size]
+        flat = np.concatenate([W1.ravel(), W2.ravel(), W3.ravel()])
+        self.W16 = torch.from_numpy(flat.astype(np.float16)).to(dev)
+        self.Wm = torch.from_numpy(flat.astype(np.float32)).to(dev)
+        self.dW = torch.zeros_like(self.Wm)
+        self.Wmm = torch.zeros_like(self.Wm)
+        self.Wvv = torch.zeros_like(self.Wm)
+        o = np.cumsum([0] + sizes)
+        shapes = [W1.shape, W2.shape, W3.shape]
+        self.Wv = [self.W16[o[i]:o[i + 1]].view(*shapes[i]) for i in range(3)]
+        self.dWv = [self.dW[o[i]:o[i + 1]].view(*shapes[i]) for i in range(3)]
+        self.feats = torch.empty((self.N, D), dtype=torch.float16, device=dev)
+        self.y = torch.empty((self.N, d_out), dtype=torch.float32, device=dev)
+        self.dy = torch.empty_like(self.y)
+        self.dfeats = torch.empty((self.N, D), dtype=torch.float32, device=dev)
+        self.ws = torch.empty(spx.spx_mlp_bwd_workspace(self.mlp, self.N), dtype=torch.uint8, device=dev)
+        self.t = 0
+        self.names = ["encode_fwd", "mlp_fwd", "mse_grad", "mlp_bwd", "encode_bwd", "adam_tables", "adam_mlp"]
+
+    def step(self, b, ev=None):
+        spx = self.spx
+        pts, tgt = self.batches[b % len(self.batches)]
+        self.t += 1
+        rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+        rec(0)
+        spx.spx_encode_fwd(self.enc, pts, self.tab16, self.feats)
+        rec(1)
+        spx.spx_mlp_fwd(self.mlp, self.feats, *self.Wv, self.y)
+        rec(2)
+        spx.spx_mse_grad(self.y, tgt, self.dy, 2.0 / (self.N * self.d_out))
+        rec(3)
+        spx.spx_mlp_bwd(self.mlp, self.feats, *self.Wv, self.dy, self.dfeats, *self.dWv, self.ws)
+        rec(4)
+        spx.spx_encode_bwd(self.enc, pts, self.dfeats, self.grad)
+        rec(5)
+        spx.spx_adam_step(self.master, self.grad, self.m, self.v, self.tab16, lr=1e-2, beta1=0.9, beta2=0.99,
+                          eps=1e-15, step=self.t, zero_grad=True)
+        rec(6)
+        spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=1e-2, beta1=0.9, beta2=0.99,
+                          eps=1e-15, step=self.t, zero_grad=False)
+        rec(7)
+
+    def algorithmic_bytes(self):
+        """Bytes each kernel must move per launch."""
+        w, N = self.w, self.N
+        n, L, F = w.n_dims, w.n_levels, w.n_feat
+        V = (1 << n) if self.enc.cell == self.spx.SPX_GRID else n + 1
+        P = L * (1 << w.log2_T) * F
+        nw = self.Wm.numel()
+        D = L * F
+        return {
+            "encode_fwd": N * (4 * n + L * V * F * 2 + D * 2),
+            "mlp_fwd": N * (2 * D + 4 * self.d_out),
+            "mse_grad": N * self.d_out * 12,
+            "mlp_bwd": N * (2 * D + 4 * self.d_out + 4 * D),
+            "encode_bwd": N * (4 * n + 4 * D + L * V * F * 8),
+            "adam_tables": P * 34,
+            "adam_mlp": nw * 34,
+        }
+
+
+def time_steps(ts, steps, warmup):
+    import torch
+    for i in range(warmup):
+        ts.step(i)
+    torch.cuda.synchronize()
+    K = len(ts.names)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(K + 1)] for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(steps):
+        ts.step(warmup + i, evs[i])
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    per = {n: float(np.mean([evs[i][k].elapsed_time(evs[i][k + 1]) for i in range(steps)]))
+           for k, n in enumerate(ts.names)}
+    return total_ms / steps, per, wall
+
+
+def time_encode_only(ts, reps=20):
+    """Encoding kernels alone (forward; adjoint) on the step's first batch."""
+    import torch
+    spx = ts.spx
+    pts, _ = ts.batches[0]
+    for _ in range(3):
+        spx.spx_encode_fwd(ts.enc, pts, ts.tab16, ts.feats)
+        spx.spx_encode_bwd(ts.enc, pts, ts.dfeats, ts.grad)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        spx.spx_encode_fwd(ts.enc, pts, ts.tab16, ts.feats)
+    e[1].record()
+    for _ in range(reps):
+        spx.spx_encode_bwd(ts.enc, pts, ts.dfeats, ts.grad)
+    e[2].record()
+    torch.cuda.synchronize()
+    ts.grad.zero_()
+    f = e[0].elapsed_time(e[1]) / reps
+    b = e[1].elapsed_time(e[2]) / reps
+    return {"fwd_ms": f, "bwd_ms": b, "fwd_points_per_s": ts.N / (f * 1e-3),
+            "fwd_bwd_points_per_s": ts.N / ((f + b) * 1e-3)}
+
+
+def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
+    """The oracle (as it stands) on a bounded sample of the same step: the
+    per-point work on S points, Adam on 1/16 of the tables; scaled to one
+    step of N points."""
+    import oracle
+    from paper_2311_15439_amd import spx as _spx  # noqa: F401  (only for the schedule helper below)
+    res = oracle.level_resolutions(w.n_min, w.growth, w.n_levels)
+    oe = oracle.Encoding(w.n_dims, list(res), w.log2_T, w.n_feat, table_dtype=oracle.F16)
+    pts, tgt = batch[0][:S], batch[1][:S]
+    tab16 = host_tables.astype(np.float16)
+    W1, W2, W3 = weights
+    t0 = time.perf_counter()
+    feats = oracle.encode_fwd(oe, pts, tab16)
+    f16 = feats.astype(np.float16)
+    y = oracle.mlp_fwd(f16, W1, W2, W3)
+    dy = oracle.mse_grad(y.astype(np.float32), tgt, 2.0 / y.size).astype(np.float32)
+    g = oracle.mlp_bwd(f16, W1, W2, W3, dy)
+    oracle.encode_bwd(oe, pts, g["d_x"])
+    t_pts = time.perf_counter() - t0
+    P = host_tables.size // 16
+    flat = host_tables.reshape(-1)[:P].astype(np.float32)
+    t0 = time.perf_counter()
+    oracle.adam_step(flat, flat * 0.01, np.zeros(P, np.float32), np.zeros(P, np.float32), 1e-2, 0.9, 0.99, 1e-15, 1)
+    t_adam = (time.perf_counter() - t0) * 16
+    t_step = t_pts * (w.n_points / S) + t_adam
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.n_points / t_step, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle training step on {S} of the {w.n_points} points ({t_pts:.2f} s) plus Adam on 1/16 "
+                      f"of the tables ({t_adam / 16:.2f} s), scaled to one {w.n_points}-point step; "
+                      f"encode fwd and MLP fwd use {threads} OpenMP threads, the rest one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="image-2d", choices=["image-2d", "volume-3d"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grid", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2311_15439_amd import inputs, spx
+    spx.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    w = _workload(args.workload)
+    d_out = 3 if w.name.startswith("image") else 4
+    print(f"# setup {w.name}: generating inputs", file=sys.stderr, flush=True)
+    host_tables = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, False)
+    weights = inputs.mlp_weights(w.n_levels * w.n_feat, 64, d_out, 9)
+    batches = []
+    for b in range(2):
+        p = _points(w, b)
+        batches.append((p, _targets(w, p, b)))
+
+    ts = TrainStep(w, spx.SPX_SIMPLEX, batches, host_tables, weights, d_out)
+    res = ts.res
+    print("# timing simplex step", file=sys.stderr, flush=True)
+    ms, per, wall = time_steps(ts, args.steps, args.warmup)
+    enc_s = time_encode_only(ts)
+    bytes_ = ts.algorithmic_bytes()
+    dom = max(per, key=per.get)
+    achieved = bytes_[dom] / (per[dom] * 1e-3) / 1e9
+    kernels = {k: {"avg_ms": round(v, 5), "algorithmic_GB_s": round(bytes_[k] / (v * 1e-3) / 1e9, 1)}
+               for k, v in per.items()}
+
+    grid = None
+    if not args.no_grid:
+        del ts
+        torch.cuda.empty_cache()
+        tg = TrainStep(w, spx.SPX_GRID, batches, host_tables, weights, d_out)
+        print("# timing grid step", file=sys.stderr, flush=True)
+        gms, gper, _ = time_steps(tg, max(5, args.steps // 2), 2)
+        genc = time_encode_only(tg)
+        grid = {"step_points_per_s": tg.N / (gms * 1e-3), "ms_per_step": gms,
+                "kernels_ms": {k: round(v, 5) for k, v in gper.items()}, "encode_only": genc}
+        del tg
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, host_tables, weights, batches[0])
+
+    value = w.n_points / (ms * 1e-3)
+    line = {
+        "metric": "encoded points/s, training step (fwd+bwd+optimizer), simplex hash encoding",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16 tables, f32 accumulate",
+        "data": "synthetic",
+        "config": {"workload": w.name + f", {w.n_points} points/step, MLP {w.n_levels * w.n_feat}-64-64-{d_out}",
+                   "levels": res, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "encode_only": {"simplex": enc_s, "grid": grid["encode_only"] if grid else None},
+        "grid_baseline_step": ({"points_per_s": grid["step_points_per_s"], "ms_per_step": grid["ms_per_step"],
+                                "kernels_ms": grid["kernels_ms"]} if grid else None),
+        "wall_s_timed": wall,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * spx.h -- C ABI of libspx.so: the multiresolution simplex hash encoding of
+ * Wen & Yang, "Efficient Encoding of Graphics Primitives with Simplex-based
+ * Structures" (arXiv 2311.15439), on AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers documented "device" address GPU memory owned by the caller
+ *     (for example torch tensors); pointers documented "host" address CPU
+ *     memory read or written during the call only.  The library never
+ *     allocates, frees or keeps a pointer after returning.
+ *   - Calls that take a hipStream_t enqueue their kernels on that stream and
+ *     return without waiting.  Argument checks happen on the host before
+ *     anything is enqueued; a call that returns an error has enqueued
+ *     nothing (SPX_EHIP excepted: the launch itself failed).
+ *   - Every call returns spx_status; no C++ exception crosses the ABI.
+ *     spx_last_error() gives a human-readable detail of the last failure on
+ *     the calling thread.
+ *   - N = 0 (no points) is a valid no-op that returns SPX_OK.
+ *   - Calls are stateless and thread-safe; results are deterministic except
+ *     where an entry point accumulates with atomics (noted below).
+ *   - Dtype codes: SPX_F32 = IEEE binary32, SPX_F16 = IEEE binary16.
+ */
+#ifndef SPX_H_
+#define SPX_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPX_ABI_VERSION 1
+#define SPX_MAX_DIMS 6
+#define SPX_MAX_LEVELS 32
+#define SPX_MAX_LOG2_T 26
+
+typedef enum {
+    SPX_OK = 0,
+    SPX_EINVAL = 1,       /* bad shape, size, dtype, flag or null pointer */
+    SPX_EALIGN = 2,       /* a device pointer lacks the documented alignment */
+    SPX_EUNSUPPORTED = 3, /* well-formed request outside what is built */
+    SPX_EHIP = 4          /* the HIP runtime reported an error at launch */
+} spx_status;
+
+enum { SPX_F32 = 0, SPX_F16 = 1 };
+enum { SPX_SIMPLEX = 0, SPX_GRID = 1 };
+
+/*
+ * Encoding descriptor (host memory, read during the call only).
+ *   n_dims       n, 1..6: dimension of the input points.
+ *   n_levels     L, 1..32: number of resolution levels.
+ *   log2_T       each level's table has T = 2^log2_T entries, 1..26.
+ *   n_feat       F, 1, 2, 4 or 8: features per table entry.
+ *   table_dtype  SPX_F32 or SPX_F16.
+ *   cell         SPX_SIMPLEX (the paper's method: n+1 vertices per level)
+ *                or SPX_GRID (the 2^n-corner multilinear baseline).
+ *   equal_memory 0 or 1: scale every level's resolution by
+ *                (n+1)^((n-1)/(2n)), the factor the paper uses to compare
+ *                simplex and grid at the same table size (Sec. 5.2).
+ *                Ignored for SPX_GRID.
+ *   res[l]       N_l >= 1, the resolution of level l (l < n_levels).
+ * Tables are laid out [L][T][F] (level-major, feature innermost) and the
+ * encoded features [N][L*F] (levels concatenated in order, Sec. 5 step (d)).
+ */
+typedef struct {
+    int32_t n_dims;
+    int32_t n_levels;
+    int32_t log2_T;
+    int32_t n_feat;
+    int32_t table_dtype;
+    int32_t cell;
+    int32_t equal_memory;
+    int32_t res[SPX_MAX_LEVELS];
+} spx_encoding;
+
+/* ABI version compiled into the library (SPX_ABI_VERSION). */
+int32_t spx_abi_version(void);
+
+/* Static string naming a status code. */
+const char* spx_status_str(spx_status s);
+
+/* Detail of the most recent failure on the calling thread ("" if none). */
+const char* spx_last_error(void);
+
+/*
+ * Host helper: geometric level schedule N_l = floor(n_min * growth^l + 1e-6)
+ * for l < L (the paper scales the unit cube per level, Sec. 5.1, without
+ * fixing the schedule).  res_out: host [L].  Errors: SPX_EINVAL if
+ * L is outside 1..32, n_min < 1, growth < 1 or res_out is NULL.
+ */
+spx_status spx_level_resolutions(double n_min, double growth, int32_t L, int32_t* res_out);
+
+/*
+ * Host helper: the binary32 multiplier sigma_l that the kernels apply to a
+ * point at level l.  Simplex: sigma_l = N_l * c / sqrt(n+1), evaluated in
+ * binary64 and rounded once, where sqrt(n+1) is the adjustment scale S_n
+ * that maps the skewed unit cube [0, S_n]^n back to [0,1]^n (Sec. 5.1) and c
+ * is the equal-memory factor or 1.  Grid: sigma_l = N_l.
+ * sigma_out: host [n_levels].
+ */
+spx_status spx_level_scales(const spx_encoding* enc, float* sigma_out);
+
+/*
+ * Host helper: the six hash multipliers P_0..P_5.  A vertex v of level l is
+ * stored at slot (XOR_i uint32(v_i) * P_i mod 2^32) & (T - 1) of that
+ * level's table (Sec. 5 steps (a)-(b); the paper does not print its hash).
+ * primes_out: host [6].
+ */
+spx_status spx_hash_primes(uint32_t* primes_out);
+
+/*
+ * Forward encoding (Sec. 5 steps (a)-(d); Secs. 4.1-4.3 for the simplex).
+ * Per point: skew (Eq. 2), then per level scale by sigma_l, split into
+ * lattice cell and fractional part, order the fractions largest first (ties
+ * to the lower axis) to pick the simplex, walk its n+1 vertices, weight
+ * them barycentrically, hash them, and sum the weighted table rows.
+ *   N        number of points, >= 0.
+ *   pts      device [N][n] binary32, 4-byte aligned.  Any finite value is
+ *            legal (the hash is total); positions are exact for
+ *            |sigma_l * skewed coordinate| < 2^24.
+ *   tables   device [L][T][F] of enc->table_dtype, aligned to one row
+ *            (F * element size, at most 16 bytes).
+ *   out      device [N][L*F] of out_dtype (SPX_F32 or SPX_F16), aligned to
+ *            F * element size (at most 16 bytes).  Overwritten.
+ * Deterministic: the same inputs give bit-identical outputs.
+ */
+spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
+                          void* out, int32_t out_dtype, hipStream_t stream);
+
+/*
+ * Adjoint of spx_encode_fwd (Sec. 5 step (e)): for every point, level and
+ * vertex, d_tables[l][h][j] += w * d_out[pt][l*F + j] with the forward's
+ * weights and slots.  There is no gradient with respect to the points.
+ *   d_out      device [N][L*F] of d_out_dtype (SPX_F32 or SPX_F16), aligned
+ *              to F * element size (at most 16 bytes).
+ *   d_tables   device [L][T][F] binary32, 4-byte aligned.  ACCUMULATED: the
+ *              caller zeroes it.  Floating-point atomics make the summation
+ *              order, and so the last bits, vary from run to run.
+ */
+spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                          int32_t d_out_dtype, float* d_tables, hipStream_t stream);
+
+/*
+ * Lookup introspection for parity tests: the slot and the binary32 weight
+ * of every vertex, from the same code the forward and adjoint use.
+ *   idx  device [N][L][V] uint32 slots (V = n+1, or 2^n for the grid whose
+ *        corners are listed in binary order, bit i standing for axis i).
+ *   w    device [N][L][V] binary32 weights.  Simplex vertices are listed in
+ *        walk order: the cell corner first, then one step along the axis of
+ *        each next-largest fraction.
+ * Either output may be NULL.
+ */
+spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts, uint32_t* idx,
+                            float* w, hipStream_t stream);
+
+/* Round-to-nearest-even binary32 -> binary16 copy of n elements (device,
+ * src 4-byte and dst 2-byte aligned). */
+spx_status spx_cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t stream);
+
+/*
+ * One Adam step (Kingma & Ba 2015, Algorithm 1; the paper trains by
+ * gradient descent without naming the optimizer) on n binary32 parameters,
+ * with bias correction for the 1-based iteration count `step`:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   param -= lr * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * All arrays are device binary32 [n], 4-byte aligned.  If param_f16 is not
+ * NULL it receives the binary16 image of the updated parameters (the table
+ * the forward gathers from).  If zero_grad is 1, grad is set to 0 after it
+ * is read, ready for the next accumulation.
+ */
+spx_status spx_adam_step(int64_t n, float* param, float* grad, float* m, float* v, uint16_t* param_f16,
+                         float lr, float beta1, float beta2, float eps, int64_t step, int32_t zero_grad,
+                         hipStream_t stream);
+
+/*
+ * Gradient of the mean squared error loss of Sec. 6 (an L2 loss against the
+ * target): d_y = scale * (y - target) elementwise over n values, with
+ * scale = 2 / n for the mean.  y, target, d_y: device binary32 [n], 4-byte
+ * aligned; d_y may alias y.
+ */
+spx_status spx_mse_grad(int64_t n, const float* y, const float* target, float* d_y, float scale,
+                        hipStream_t stream);
+
+/*
+ * Tiny fully connected network of Sec. 5 step (e): d_in -> hidden -> hidden
+ * -> d_out, ReLU after the two hidden layers, linear output.
+ *   d_in    32 (the concatenated features, L*F; other widths return
+ *           SPX_EUNSUPPORTED).
+ *   hidden  64.
+ *   d_out   1..16.
+ * Weights are binary16, row-major, device, 16-byte aligned:
+ * W1 [hidden][d_in], W2 [hidden][hidden], W3 [d_out][hidden].
+ */
+typedef struct {
+    int32_t d_in;
+    int32_t hidden;
+    int32_t d_out;
+} spx_mlp;
+
+/*
+ * Forward pass.  x: device [N][d_in] binary16, 16-byte aligned;
+ * y: device [N][d_out] binary32, 4-byte aligned, overwritten.  Products run
+ * on the matrix cores in binary16 with binary32 accumulation; hidden
+ * activations are rounded to binary16.  Deterministic.
+ */
+spx_status spx_mlp_fwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1,
+                       const uint16_t* W2, const uint16_t* W3, float* y, hipStream_t stream);
+
+/*
+ * Workspace needed by spx_mlp_bwd for N points (bytes, written to *bytes).
+ */
+spx_status spx_mlp_bwd_workspace(const spx_mlp* mlp, int64_t N, size_t* bytes);
+
+/*
+ * Backward pass (recomputes the forward).  d_y: device [N][d_out] binary32.
+ * d_x: device [N][d_in] binary32, overwritten, or NULL to skip.
+ * dW1/dW2/dW3: device binary32 with the weights' shapes, OVERWRITTEN with
+ * the gradient summed over the N points.  Gradient operands are rounded to
+ * bfloat16 for the matrix cores (binary32 accumulation); the ReLU mask is
+ * taken on the stored binary16 activation.  workspace: device, at least
+ * spx_mlp_bwd_workspace() bytes, 256-byte aligned.  The weight-gradient
+ * sum is reduced in a fixed order: deterministic.
+ */
+spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1,
+                       const uint16_t* W2, const uint16_t* W3, const float* d_y, float* d_x, float* dW1,
+                       float* dW2, float* dW3, void* workspace, size_t workspace_bytes,
+                       hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPX_H_ */

@@ -76,6 +76,7 @@ def lib():
             ("orc_adam_step", None, [C.c_int64, P, P, P, P, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_int64, P]),
             ("orc_cast_f32_f16", None, [C.c_int64, P, P]),
+            ("orc_mse_grad", None, [C.c_int64, P, P, C.c_double, P]),
         ]:
             fn = getattr(L, name)
             fn.restype = res
@@ -276,6 +277,14 @@ def adam_step(param, grad, m, v, lr, beta1, beta2, eps, step):
     h = np.zeros(p.shape, np.uint16)
     lib().orc_adam_step(p.size, _p(p), _p(g), _p(mm), _p(vv), lr, beta1, beta2, eps, step, _p(h))
     return p, mm, vv, h
+
+
+def mse_grad(y, target, scale: float) -> np.ndarray:
+    a = np.ascontiguousarray(y, np.float32)
+    b = np.ascontiguousarray(target, np.float32)
+    out = np.zeros(a.shape, np.float64)
+    lib().orc_mse_grad(a.size, _p(a), _p(b), float(scale), _p(out))
+    return out
 
 
 def cast_f32_f16(src) -> np.ndarray:

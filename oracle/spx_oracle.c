@@ -570,6 +570,12 @@ void orc_adam_step(int64_t n, float* param, const float* grad, float* m, float* 
     }
 }
 
+/* Gradient of the mean squared error (Sec. 6 trains with an L2 loss):
+ * d_y = scale * (y - target), binary64 from binary32 inputs. */
+void orc_mse_grad(int64_t n, const float* y, const float* target, double scale, double* d_y) {
+    for (int64_t i = 0; i < n; ++i) d_y[i] = scale * ((double)y[i] - (double)target[i]);
+}
+
 /* Round-to-nearest-even binary32 -> binary16 copy. */
 void orc_cast_f32_f16(int64_t n, const float* src, uint16_t* dst) {
     for (int64_t i = 0; i < n; ++i) dst[i] = orc_f64_to_f16((double)src[i]);

@@ -1,0 +1,324 @@
+// C ABI of libspx.so (declared in include/spx.h): argument checks, the
+// host-side constants (level multipliers, skew factor), and dispatch to the
+// kernel translation units.  No allocation, no synchronisation.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "spx.h"
+#include "lookup.hpp"
+#include "spx_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+spx_status fail(spx_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+spx_status from_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SPX_OK;
+    return fail(SPX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t row_align(int F, int elem) {
+    size_t b = (size_t)F * elem;
+    return b > 16 ? 16 : b;
+}
+
+spx_status check_encoding(const spx_encoding* e) {
+    if (!e) return fail(SPX_EINVAL, "encoding descriptor is NULL");
+    if (e->n_dims < 1 || e->n_dims > SPX_MAX_DIMS) return fail(SPX_EINVAL, "n_dims=%d outside 1..%d", e->n_dims, SPX_MAX_DIMS);
+    if (e->n_levels < 1 || e->n_levels > SPX_MAX_LEVELS)
+        return fail(SPX_EINVAL, "n_levels=%d outside 1..%d", e->n_levels, SPX_MAX_LEVELS);
+    if (e->log2_T < 1 || e->log2_T > SPX_MAX_LOG2_T)
+        return fail(SPX_EINVAL, "log2_T=%d outside 1..%d", e->log2_T, SPX_MAX_LOG2_T);
+    if (e->n_feat != 1 && e->n_feat != 2 && e->n_feat != 4 && e->n_feat != 8)
+        return fail(SPX_EINVAL, "n_feat=%d not in {1,2,4,8}", e->n_feat);
+    if (e->table_dtype != SPX_F32 && e->table_dtype != SPX_F16)
+        return fail(SPX_EINVAL, "table_dtype=%d is not SPX_F32 or SPX_F16", e->table_dtype);
+    if (e->cell != SPX_SIMPLEX && e->cell != SPX_GRID) return fail(SPX_EINVAL, "cell=%d unknown", e->cell);
+    if (e->equal_memory != 0 && e->equal_memory != 1) return fail(SPX_EINVAL, "equal_memory must be 0 or 1");
+    for (int l = 0; l < e->n_levels; ++l)
+        if (e->res[l] < 1) return fail(SPX_EINVAL, "res[%d]=%d < 1", l, e->res[l]);
+    return SPX_OK;
+}
+
+void level_scales(const spx_encoding* e, float* sigma) {
+    const int n = e->n_dims;
+    const double S = sqrt((double)n + 1.0);
+    const double c = (e->equal_memory && e->cell == SPX_SIMPLEX)
+                         ? pow((double)n + 1.0, (double)(n - 1) / (2.0 * (double)n))
+                         : 1.0;
+    for (int l = 0; l < e->n_levels; ++l) {
+        if (e->cell == SPX_GRID)
+            sigma[l] = (float)(double)e->res[l];
+        else
+            sigma[l] = (float)(((double)e->res[l] * c) / S);
+    }
+}
+
+spx::LevelArgs level_args(const spx_encoding* e) {
+    spx::LevelArgs lv;
+    memset(&lv, 0, sizeof(lv));
+    level_scales(e, lv.sigma);
+    const int n = e->n_dims;
+    lv.Fn = (float)((sqrt((double)n + 1.0) - 1.0) / (double)n);
+    lv.mask = (uint32_t)((1ull << e->log2_T) - 1ull);
+    lv.L = e->n_levels;
+    return lv;
+}
+
+spx::EncodeCall base_call(const spx_encoding* e, int64_t N, const float* pts, hipStream_t s) {
+    spx::EncodeCall c;
+    memset(&c, 0, sizeof(c));
+    c.D = e->n_dims;
+    c.F = e->n_feat;
+    c.table_f16 = e->table_dtype == SPX_F16;
+    c.N = N;
+    c.pts = pts;
+    c.lv = level_args(e);
+    c.stream = s;
+    return c;
+}
+
+hipError_t run(const spx_encoding* e, const spx::EncodeCall& c) {
+    return e->cell == SPX_GRID ? spx::encode_grid(c) : spx::encode_simplex(c);
+}
+
+spx_status check_points(int64_t N, const float* pts) {
+    if (N < 0) return fail(SPX_EINVAL, "N=%lld < 0", (long long)N);
+    if (N > 0 && !pts) return fail(SPX_EINVAL, "pts is NULL");
+    if (pts && !aligned(pts, 4)) return fail(SPX_EALIGN, "pts not 4-byte aligned");
+    return SPX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t spx_abi_version(void) { return SPX_ABI_VERSION; }
+
+const char* spx_status_str(spx_status s) {
+    switch (s) {
+        case SPX_OK: return "SPX_OK";
+        case SPX_EINVAL: return "SPX_EINVAL: invalid argument";
+        case SPX_EALIGN: return "SPX_EALIGN: misaligned device pointer";
+        case SPX_EUNSUPPORTED: return "SPX_EUNSUPPORTED: configuration not built";
+        case SPX_EHIP: return "SPX_EHIP: HIP runtime error";
+    }
+    return "unknown spx_status";
+}
+
+const char* spx_last_error(void) { return g_err; }
+
+spx_status spx_level_resolutions(double n_min, double growth, int32_t L, int32_t* res_out) {
+    if (L < 1 || L > SPX_MAX_LEVELS) return fail(SPX_EINVAL, "L=%d outside 1..%d", L, SPX_MAX_LEVELS);
+    if (!(n_min >= 1.0) || !(growth >= 1.0)) return fail(SPX_EINVAL, "n_min and growth must be >= 1");
+    if (!res_out) return fail(SPX_EINVAL, "res_out is NULL");
+    for (int l = 0; l < L; ++l) {
+        const double v = floor(n_min * pow(growth, (double)l) + 1e-6);
+        if (v > 2147483647.0) return fail(SPX_EINVAL, "level %d resolution overflows int32", l);
+        res_out[l] = (int32_t)v;
+    }
+    return SPX_OK;
+}
+
+spx_status spx_level_scales(const spx_encoding* enc, float* sigma_out) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if (!sigma_out) return fail(SPX_EINVAL, "sigma_out is NULL");
+    level_scales(enc, sigma_out);
+    return SPX_OK;
+}
+
+spx_status spx_hash_primes(uint32_t* primes_out) {
+    if (!primes_out) return fail(SPX_EINVAL, "primes_out is NULL");
+    for (int i = 0; i < SPX_MAX_DIMS; ++i) primes_out[i] = spx::hash_prime(i);
+    return SPX_OK;
+}
+
+spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, const void* tables, void* out,
+                          int32_t out_dtype, hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (out_dtype != SPX_F32 && out_dtype != SPX_F16) return fail(SPX_EINVAL, "out_dtype=%d", out_dtype);
+    if (N == 0) return SPX_OK;
+    if (!tables || !out) return fail(SPX_EINVAL, "tables or out is NULL");
+    const int te = enc->table_dtype == SPX_F16 ? 2 : 4, oe = out_dtype == SPX_F16 ? 2 : 4;
+    if (!aligned(tables, row_align(enc->n_feat, te))) return fail(SPX_EALIGN, "tables not row-aligned");
+    if (!aligned(out, row_align(enc->n_feat, oe))) return fail(SPX_EALIGN, "out not row-aligned");
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::Forward;
+    c.out_f16 = out_dtype == SPX_F16;
+    c.tables = tables;
+    c.out = out;
+    return from_hip(run(enc, c), "spx_encode_fwd launch");
+}
+
+spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                          int32_t d_out_dtype, float* d_tables, hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (d_out_dtype != SPX_F32 && d_out_dtype != SPX_F16) return fail(SPX_EINVAL, "d_out_dtype=%d", d_out_dtype);
+    if (N == 0) return SPX_OK;
+    if (!d_out || !d_tables) return fail(SPX_EINVAL, "d_out or d_tables is NULL");
+    const int ge = d_out_dtype == SPX_F16 ? 2 : 4;
+    if (!aligned(d_out, row_align(enc->n_feat, ge))) return fail(SPX_EALIGN, "d_out not row-aligned");
+    if (!aligned(d_tables, 4)) return fail(SPX_EALIGN, "d_tables not 4-byte aligned");
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::Adjoint;
+    c.dout_f16 = d_out_dtype == SPX_F16;
+    c.d_out = d_out;
+    c.d_tables = d_tables;
+    return from_hip(run(enc, c), "spx_encode_bwd launch");
+}
+
+spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts, uint32_t* idx, float* w,
+                            hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (N == 0 || (!idx && !w)) return SPX_OK;
+    if ((idx && !aligned(idx, 4)) || (w && !aligned(w, 4))) return fail(SPX_EALIGN, "idx/w not 4-byte aligned");
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::Debug;
+    c.idx = idx;
+    c.w = w;
+    return from_hip(run(enc, c), "spx_encode_debug launch");
+}
+
+spx_status spx_cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t stream) {
+    if (n < 0) return fail(SPX_EINVAL, "n < 0");
+    if (n == 0) return SPX_OK;
+    if (!src || !dst) return fail(SPX_EINVAL, "src or dst is NULL");
+    if (!aligned(src, 4) || !aligned(dst, 2)) return fail(SPX_EALIGN, "src/dst misaligned");
+    return from_hip(spx::cast_f32_f16(n, src, dst, stream), "spx_cast_f32_f16 launch");
+}
+
+spx_status spx_adam_step(int64_t n, float* param, float* grad, float* m, float* v, uint16_t* param_f16, float lr,
+                         float beta1, float beta2, float eps, int64_t step, int32_t zero_grad, hipStream_t stream) {
+    if (n < 0) return fail(SPX_EINVAL, "n < 0");
+    if (step < 1) return fail(SPX_EINVAL, "step=%lld < 1", (long long)step);
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return fail(SPX_EINVAL, "beta1/beta2 must lie in [0,1) and eps >= 0");
+    if (zero_grad != 0 && zero_grad != 1) return fail(SPX_EINVAL, "zero_grad must be 0 or 1");
+    if (n == 0) return SPX_OK;
+    if (!param || !grad || !m || !v) return fail(SPX_EINVAL, "param, grad, m or v is NULL");
+    if (!aligned(param, 4) || !aligned(grad, 4) || !aligned(m, 4) || !aligned(v, 4) || (param_f16 && !aligned(param_f16, 2)))
+        return fail(SPX_EALIGN, "Adam state misaligned");
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
+    return from_hip(spx::adam_step(n, param, grad, m, v, param_f16, lr, beta1, beta2, eps, bc1, bc2, zero_grad, stream),
+                    "spx_adam_step launch");
+}
+
+spx_status spx_mse_grad(int64_t n, const float* y, const float* target, float* d_y, float scale,
+                        hipStream_t stream) {
+    if (n < 0) return fail(SPX_EINVAL, "n < 0");
+    if (n == 0) return SPX_OK;
+    if (!y || !target || !d_y) return fail(SPX_EINVAL, "NULL pointer");
+    if (!aligned(y, 4) || !aligned(target, 4) || !aligned(d_y, 4)) return fail(SPX_EALIGN, "misaligned");
+    return from_hip(spx::mse_grad(n, y, target, d_y, scale, stream), "spx_mse_grad launch");
+}
+
+static spx_status check_mlp(const spx_mlp* mlp, int64_t N) {
+    if (!mlp) return fail(SPX_EINVAL, "mlp descriptor is NULL");
+    if (N < 0) return fail(SPX_EINVAL, "N < 0");
+    if (mlp->hidden != 64) return fail(SPX_EUNSUPPORTED, "hidden=%d (built: 64)", mlp->hidden);
+    if (mlp->d_in != 32) return fail(SPX_EUNSUPPORTED, "d_in=%d (built: 32)", mlp->d_in);
+    if (mlp->d_out < 1 || mlp->d_out > 16) return fail(SPX_EINVAL, "d_out=%d outside 1..16", mlp->d_out);
+    return SPX_OK;
+}
+
+spx_status spx_mlp_fwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1, const uint16_t* W2,
+                       const uint16_t* W3, float* y, hipStream_t stream) {
+    spx_status st = check_mlp(mlp, N);
+    if (st) return st;
+    if (N == 0) return SPX_OK;
+    if (!x || !W1 || !W2 || !W3 || !y) return fail(SPX_EINVAL, "NULL pointer");
+    if (!aligned(x, 16) || !aligned(W1, 16) || !aligned(W2, 16) || !aligned(W3, 16) || !aligned(y, 4))
+        return fail(SPX_EALIGN, "x/W must be 16-byte and y 4-byte aligned");
+    spx::MlpCall c;
+    memset(&c, 0, sizeof(c));
+    c.d_in = mlp->d_in;
+    c.hidden = mlp->hidden;
+    c.d_out = mlp->d_out;
+    c.N = N;
+    c.x = x;
+    c.W1 = W1;
+    c.W2 = W2;
+    c.W3 = W3;
+    c.y = y;
+    c.stream = stream;
+    return from_hip(spx::mlp_fwd(c), "spx_mlp_fwd launch");
+}
+
+spx_status spx_mlp_bwd_workspace(const spx_mlp* mlp, int64_t N, size_t* bytes) {
+    spx_status st = check_mlp(mlp, N);
+    if (st) return st;
+    if (!bytes) return fail(SPX_EINVAL, "bytes is NULL");
+    *bytes = spx::mlp_bwd_workspace_bytes(mlp->d_in, mlp->hidden, mlp->d_out, N);
+    return SPX_OK;
+}
+
+spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1, const uint16_t* W2,
+                       const uint16_t* W3, const float* d_y, float* d_x, float* dW1, float* dW2, float* dW3,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    spx_status st = check_mlp(mlp, N);
+    if (st) return st;
+    if (!W1 || !W2 || !W3 || !dW1 || !dW2 || !dW3) return fail(SPX_EINVAL, "NULL weight pointer");
+    if (N > 0 && (!x || !d_y)) return fail(SPX_EINVAL, "x or d_y is NULL");
+    const size_t need = spx::mlp_bwd_workspace_bytes(mlp->d_in, mlp->hidden, mlp->d_out, N);
+    if (!workspace || workspace_bytes < need)
+        return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    if (!aligned(x, 16) || !aligned(W1, 16) || !aligned(W2, 16) || !aligned(W3, 16) || !aligned(d_y, 4) ||
+        (d_x && !aligned(d_x, 16)) || !aligned(dW1, 4) || !aligned(dW2, 4) || !aligned(dW3, 4) ||
+        !aligned(workspace, 256))
+        return fail(SPX_EALIGN, "misaligned MLP backward argument");
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return from_hip(he, "hipGetDevice");
+    static int lds_cache[64];  // per-device limit, looked up once (benign race: same value)
+    int lds_max = dev < 64 ? lds_cache[dev] : 0;
+    if (lds_max == 0) {
+        he = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (he != hipSuccess) return from_hip(he, "hipDeviceGetAttribute");
+        if (dev < 64) lds_cache[dev] = lds_max;
+    }
+    if (spx::mlp_bwd_lds_bytes(mlp->d_in) > lds_max)
+        return fail(SPX_EUNSUPPORTED, "MLP backward needs %d bytes of LDS, device allows %d",
+                    spx::mlp_bwd_lds_bytes(mlp->d_in), lds_max);
+    spx::MlpCall c;
+    memset(&c, 0, sizeof(c));
+    c.d_in = mlp->d_in;
+    c.hidden = mlp->hidden;
+    c.d_out = mlp->d_out;
+    c.N = N;
+    c.x = x;
+    c.W1 = W1;
+    c.W2 = W2;
+    c.W3 = W3;
+    c.d_y = d_y;
+    c.d_x = d_x;
+    c.dW1 = dW1;
+    c.dW2 = dW2;
+    c.dW3 = dW3;
+    c.workspace = workspace;
+    c.stream = stream;
+    return from_hip(spx::mlp_bwd(c), "spx_mlp_bwd launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,279 @@
+// Forward, adjoint and debug kernels of the multiresolution hash encoding,
+// generic over the cell (simplex or 2^n-corner grid), the dimension, the
+// feature count and the storage types.  One thread handles one point and
+// walks all levels: the point is loaded and skewed once, and the L*F
+// outputs of a point are produced by the same thread.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lookup.hpp"
+#include "spx_internal.h"
+
+namespace spx {
+
+typedef _Float16 f16;
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---- one table row / one output row of F values -------------------------
+
+template <typename T, int F>
+struct RowIO;
+
+template <int F>
+struct RowIO<float, F> {
+    __device__ __forceinline__ static void load(const float* __restrict__ p, float (&v)[F]) {
+        if constexpr (F == 1) {
+            v[0] = p[0];
+        } else if constexpr (F == 2) {
+            f32x2 q = *reinterpret_cast<const f32x2*>(p);
+            v[0] = q.x; v[1] = q.y;
+        } else {
+#pragma unroll
+            for (int c = 0; c < F / 4; ++c) {
+                f32x4 q = reinterpret_cast<const f32x4*>(p)[c];
+                v[4 * c] = q.x; v[4 * c + 1] = q.y; v[4 * c + 2] = q.z; v[4 * c + 3] = q.w;
+            }
+        }
+    }
+    __device__ __forceinline__ static void store(float* __restrict__ p, const float (&v)[F]) {
+        if constexpr (F == 1) {
+            p[0] = v[0];
+        } else if constexpr (F == 2) {
+            *reinterpret_cast<f32x2*>(p) = f32x2{v[0], v[1]};
+        } else {
+#pragma unroll
+            for (int c = 0; c < F / 4; ++c)
+                reinterpret_cast<f32x4*>(p)[c] = f32x4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
+        }
+    }
+};
+
+template <int F>
+struct RowIO<f16, F> {
+    __device__ __forceinline__ static void load(const f16* __restrict__ p, float (&v)[F]) {
+        if constexpr (F == 1) {
+            v[0] = (float)p[0];
+        } else if constexpr (F == 2) {
+            f16x2 q = *reinterpret_cast<const f16x2*>(p);
+            v[0] = (float)q.x; v[1] = (float)q.y;
+        } else if constexpr (F == 4) {
+            f16x4 q = *reinterpret_cast<const f16x4*>(p);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = (float)q[j];
+        } else {
+            f16x8 q = *reinterpret_cast<const f16x8*>(p);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (float)q[j];
+        }
+    }
+    __device__ __forceinline__ static void store(f16* __restrict__ p, const float (&v)[F]) {
+        if constexpr (F == 1) {
+            p[0] = (f16)v[0];
+        } else if constexpr (F == 2) {
+            *reinterpret_cast<f16x2*>(p) = f16x2{(f16)v[0], (f16)v[1]};
+        } else if constexpr (F == 4) {
+            *reinterpret_cast<f16x4*>(p) = f16x4{(f16)v[0], (f16)v[1], (f16)v[2], (f16)v[3]};
+        } else {
+            f16x8 q;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) q[j] = (f16)v[j];
+            *reinterpret_cast<f16x8*>(p) = q;
+        }
+    }
+};
+
+// ---- visiting the vertices of one level ---------------------------------
+// fn(h, w, base) is called with arrays of K slots and weights; base is the
+// index of the first of them in the level's vertex list.
+
+template <int D, class Fn>
+__device__ __forceinline__ void visit_level(SimplexTag, const float (&y)[D], float sigma, uint32_t mask,
+                                            Fn&& fn) {
+    uint32_t h[D + 1];
+    float w[D + 1];
+    SimplexCell<D>::lookup(y, sigma, mask, h, w);
+    fn(h, w, 0);
+}
+
+template <int D, class Fn>
+__device__ __forceinline__ void visit_level(GridTag, const float (&x)[D], float sigma, uint32_t mask,
+                                            Fn&& fn) {
+    typename GridCell<D>::Low lo;
+    GridCell<D>::lookup_low(x, sigma, lo);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        uint32_t h[GridCell<D>::VH];
+        float w[GridCell<D>::VH];
+        GridCell<D>::corners(lo, half, mask, h, w);
+        fn(h, w, half * GridCell<D>::VH);
+    }
+}
+
+template <class Tag, int D>
+__device__ __forceinline__ void load_point(const float* __restrict__ pts, int64_t pt, float Fn, float (&y)[D]) {
+    float x[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) x[i] = pts[pt * D + i];
+    if constexpr (Tag::simplex) {
+        skew<D>(x, Fn, y);
+    } else {
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = x[i];
+    }
+}
+
+constexpr int kBlock = 256;
+
+// ---- forward ------------------------------------------------------------
+
+template <class Tag, int D, int F, typename TT, typename OT>
+__global__ __launch_bounds__(kBlock) void encode_fwd_kernel(int64_t N, const float* __restrict__ pts,
+                                                            const TT* __restrict__ tables, OT* __restrict__ out,
+                                                            LevelArgs lv) {
+    const uint32_t mask = lv.mask;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        OT* __restrict__ orow = out + pt * (int64_t)(lv.L * F);
+        for (int l = 0; l < lv.L; ++l) {
+            const TT* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * F);
+            float acc[F];
+#pragma unroll
+            for (int j = 0; j < F; ++j) acc[j] = 0.0f;
+            visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto& w, int) {
+                constexpr int K = sizeof(w) / sizeof(float);
+                float v[K][F];
+#pragma unroll
+                for (int k = 0; k < K; ++k) RowIO<TT, F>::load(tab + (size_t)h[k] * F, v[k]);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int j = 0; j < F; ++j) acc[j] = __builtin_fmaf(w[k], v[k][j], acc[j]);
+            });
+            RowIO<OT, F>::store(orow + l * F, acc);
+        }
+    }
+}
+
+// ---- adjoint ------------------------------------------------------------
+
+template <class Tag, int D, int F, typename GT>
+__global__ __launch_bounds__(kBlock) void encode_bwd_kernel(int64_t N, const float* __restrict__ pts,
+                                                            const GT* __restrict__ d_out,
+                                                            float* __restrict__ d_tables, LevelArgs lv) {
+    const uint32_t mask = lv.mask;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        const GT* __restrict__ grow = d_out + pt * (int64_t)(lv.L * F);
+        for (int l = 0; l < lv.L; ++l) {
+            float g[F];
+            RowIO<GT, F>::load(grow + l * F, g);
+            float* __restrict__ tab = d_tables + (size_t)l * ((size_t)(mask + 1u) * F);
+            visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto& w, int) {
+                constexpr int K = sizeof(w) / sizeof(float);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int j = 0; j < F; ++j) unsafeAtomicAdd(tab + (size_t)h[k] * F + j, w[k] * g[j]);
+            });
+        }
+    }
+}
+
+// ---- debug --------------------------------------------------------------
+
+template <class Tag, int D>
+__global__ __launch_bounds__(kBlock) void encode_debug_kernel(int64_t N, const float* __restrict__ pts,
+                                                              uint32_t* __restrict__ idx,
+                                                              float* __restrict__ wout, LevelArgs lv) {
+    const uint32_t mask = lv.mask;
+    constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        for (int l = 0; l < lv.L; ++l) {
+            const int64_t base = (pt * lv.L + l) * V;
+            visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto& w, int b0) {
+                constexpr int K = sizeof(w) / sizeof(float);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (idx) idx[base + b0 + k] = h[k];
+                    if (wout) wout[base + b0 + k] = w[k];
+                }
+            });
+        }
+    }
+}
+
+// ---- dispatch -------------------------------------------------------------
+
+inline unsigned grid_for(int64_t N) {
+    int64_t blocks = (N + kBlock - 1) / kBlock;
+    const int64_t cap = 1 << 20;
+    return (unsigned)(blocks < cap ? (blocks > 0 ? blocks : 1) : cap);
+}
+
+template <class Tag, int D, int F>
+hipError_t fwd_dispatch_types(const EncodeCall& c) {
+    dim3 g(grid_for(c.N)), b(kBlock);
+    if (c.table_f16 && c.out_f16)
+        encode_fwd_kernel<Tag, D, F, f16, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (f16*)c.out, c.lv);
+    else if (c.table_f16)
+        encode_fwd_kernel<Tag, D, F, f16, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (float*)c.out, c.lv);
+    else if (c.out_f16)
+        encode_fwd_kernel<Tag, D, F, float, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (f16*)c.out, c.lv);
+    else
+        encode_fwd_kernel<Tag, D, F, float, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (float*)c.out, c.lv);
+    return hipGetLastError();
+}
+
+template <class Tag, int D, int F>
+hipError_t bwd_dispatch_types(const EncodeCall& c) {
+    dim3 g(grid_for(c.N)), b(kBlock);
+    if (c.dout_f16)
+        encode_bwd_kernel<Tag, D, F, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.d_out, c.d_tables, c.lv);
+    else
+        encode_bwd_kernel<Tag, D, F, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.d_out, c.d_tables, c.lv);
+    return hipGetLastError();
+}
+
+template <class Tag, int D>
+hipError_t dispatch_F(const EncodeCall& c) {
+    if (c.op == EncodeOp::Debug) {
+        encode_debug_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, c.idx, c.w, c.lv);
+        return hipGetLastError();
+    }
+    const bool fwd = c.op == EncodeOp::Forward;
+    switch (c.F) {
+        case 1: return fwd ? fwd_dispatch_types<Tag, D, 1>(c) : bwd_dispatch_types<Tag, D, 1>(c);
+        case 2: return fwd ? fwd_dispatch_types<Tag, D, 2>(c) : bwd_dispatch_types<Tag, D, 2>(c);
+        case 4: return fwd ? fwd_dispatch_types<Tag, D, 4>(c) : bwd_dispatch_types<Tag, D, 4>(c);
+        case 8: return fwd ? fwd_dispatch_types<Tag, D, 8>(c) : bwd_dispatch_types<Tag, D, 8>(c);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Tag>
+hipError_t dispatch_D(const EncodeCall& c) {
+    switch (c.D) {
+        case 1: return dispatch_F<Tag, 1>(c);
+        case 2: return dispatch_F<Tag, 2>(c);
+        case 3: return dispatch_F<Tag, 3>(c);
+        case 4: return dispatch_F<Tag, 4>(c);
+        case 5: return dispatch_F<Tag, 5>(c);
+        case 6: return dispatch_F<Tag, 6>(c);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace spx

@@ -1,0 +1,6 @@
+// Simplex-cell instantiation of the encoding kernels (the paper's method).
+#include "encode_kernels.hpp"
+
+namespace spx {
+hipError_t encode_simplex(const EncodeCall& c) { return dispatch_D<SimplexTag>(c); }
+}  // namespace spx

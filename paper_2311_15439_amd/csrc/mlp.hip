@@ -1,0 +1,432 @@
+// Tiny fully connected network on the matrix cores (Sec. 5 step (e)):
+// d_in -> 64 -> 64 -> d_out, ReLU on the hidden layers, linear output.
+//
+// Layout strategy.  Every product is computed transposed, Out^T = W In^T,
+// with the 16x16x32 MFMA: the 16 columns are 16 points, the 16 rows are
+// output units.  An MFMA result leaves lane (r, q) = (lane % 16, lane / 16)
+// holding point r and units 4q..4q+3 of a 16-unit tile.  Because A and B
+// of one MFMA share the same assignment of k to (lane group, item), two
+// such 16-unit tiles can feed the next layer's 32-deep k step directly, as
+// long as the weight fragments are loaded with the matching k order:
+//   chained k order:  item j of group q  ->  unit j<4 ? 4q+j : 16+4q+(j-4)
+//   loaded k order:   item j of group q  ->  unit 8q+j   (operands read
+//                                            from memory or LDS)
+// So activations never leave registers between layers.  The weight
+// gradients contract over points, which live one per lane; those operands
+// are transposed through LDS.
+//
+// Precision: forward products in binary16 with binary32 accumulation,
+// hidden activations rounded to binary16; backward products in bfloat16
+// with binary32 accumulation; the ReLU mask is taken on the stored binary16
+// activation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spx_internal.h"
+
+namespace spx {
+namespace {
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int H = 64;  // hidden width
+
+__device__ __forceinline__ f4 mma_h(h8 a, h8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma_b(b8 a, b8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int k_chain(int q, int j) { return j < 4 ? 4 * q + j : 16 + 4 * q + (j - 4); }
+__device__ __forceinline__ int k_load(int q, int j) { return 8 * q + j; }
+
+// ReLU then round to binary16 (the stored activation).
+__device__ __forceinline__ h4 relu_h(f4 c) {
+    return h4{(_Float16)fmaxf(c.x, 0.0f), (_Float16)fmaxf(c.y, 0.0f), (_Float16)fmaxf(c.z, 0.0f),
+              (_Float16)fmaxf(c.w, 0.0f)};
+}
+__device__ __forceinline__ h8 cat_h(h4 a, h4 b) { return h8{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}; }
+__device__ __forceinline__ b8 cat_b(f4 a, f4 b) {
+    return b8{(__bf16)a.x, (__bf16)a.y, (__bf16)a.z, (__bf16)a.w,
+              (__bf16)b.x, (__bf16)b.y, (__bf16)b.z, (__bf16)b.w};
+}
+
+// ------------------------------------------------------------------ forward
+
+template <int DIN>
+__global__ __launch_bounds__(256) void mlp_fwd_kernel(int64_t N, const _Float16* __restrict__ x,
+                                                      const _Float16* __restrict__ W1,
+                                                      const _Float16* __restrict__ W2,
+                                                      const _Float16* __restrict__ W3, int d_out,
+                                                      float* __restrict__ y) {
+    constexpr int KS1 = DIN / 32;  // k steps of layer 1
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    h8 w1[4][KS1], w2[4][2], w3[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < KS1; ++s)
+            w1[t][s] = *reinterpret_cast<const h8*>(W1 + (16 * t + r) * DIN + 32 * s + 8 * q);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w2[t][s][j] = W2[(16 * t + r) * H + 32 * s + k_chain(q, j)];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w3[s][j] = r < d_out ? W3[r * H + 32 * s + k_chain(q, j)] : (_Float16)0.0f;
+
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t ntiles = (N + 15) / 16;
+    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+        const int64_t p = tile * 16 + r;
+        const bool valid = p < N;
+        h8 xb[KS1];
+#pragma unroll
+        for (int s = 0; s < KS1; ++s)
+            xb[s] = valid ? *reinterpret_cast<const h8*>(x + p * DIN + 32 * s + 8 * q) : h8{};
+        h4 h1[4], h2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS1; ++s) c = mma_h(w1[t][s], xb[s], c);
+            h1[t] = relu_h(c);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) c = mma_h(w2[t][s], cat_h(h1[2 * s], h1[2 * s + 1]), c);
+            h2[t] = relu_h(c);
+        }
+        f4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) o = mma_h(w3[s], cat_h(h2[2 * s], h2[2 * s + 1]), o);
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (4 * q + i < d_out) y[p * d_out + 4 * q + i] = o[i];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- backward
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// 16x16x16 bfloat16 MFMA for the weight gradients (k = 16 points).
+__device__ __forceinline__ f4 mma_b16(s4 a, s4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ short bf_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
+
+constexpr int kBwdWaves = 4;
+constexpr int kPts = 16;  // points per wave per iteration
+constexpr int kMaxBwdGroups = 512;
+
+template <int DIN>
+struct BwdLayout {
+    // weight fragments, 16 bytes per lane each
+    static constexpr int F_W1 = 0;                      // [4][DIN/32] f16, loaded k order
+    static constexpr int F_W2 = F_W1 + 4 * (DIN / 32);  // [4][2] f16, chained k order
+    static constexpr int F_W3T = F_W2 + 8;              // [4] bf16, loaded k order (outputs padded to 32)
+    static constexpr int F_W2T = F_W3T + 4;             // [4][2] bf16, chained
+    static constexpr int F_W1T = F_W2T + 8;             // [DIN/16][2] bf16, chained
+    static constexpr int NFRAG = F_W1T + 2 * (DIN / 16);
+    static constexpr int FRAG_BYTES = NFRAG * 64 * 16;
+    // per-wave transpose area: one row of 16 points (bf16) per unit
+    static constexpr int R_DY = 0, R_H2 = 16, R_H1 = 80, R_DA2 = 144, R_DA1 = 208;
+    static constexpr int ROWS = 272;
+    static constexpr int WAVE_BYTES = ROWS * kPts * 2;
+    static constexpr int PARTIAL = H * DIN + H * H + 16 * H;  // floats per workgroup
+    static constexpr int AREA = kBwdWaves * WAVE_BYTES > PARTIAL * 4 ? kBwdWaves * WAVE_BYTES : PARTIAL * 4;
+    static constexpr int LDS_BYTES = FRAG_BYTES + AREA;
+};
+
+template <int DIN>
+__global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16* __restrict__ x,
+                                                      const _Float16* __restrict__ W1,
+                                                      const _Float16* __restrict__ W2,
+                                                      const _Float16* __restrict__ W3, int d_out,
+                                                      const float* __restrict__ d_y, float* __restrict__ d_x,
+                                                      float* __restrict__ partial) {
+    using Lay = BwdLayout<DIN>;
+    constexpr int KS1 = DIN / 32;
+    constexpr int TIN = DIN / 16;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    uint4* frag = reinterpret_cast<uint4*>(lds);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, r = lane & 15, q = lane >> 4, wv = tid >> 6;
+
+    // ---- stage the weight fragments (each wave builds a quarter of them)
+    for (int f = wv; f < Lay::NFRAG; f += kBwdWaves) {
+        uint4 v;
+        if (f < Lay::F_W2) {
+            const int t = (f - Lay::F_W1) / KS1, s = (f - Lay::F_W1) % KS1;
+            h8 a = *reinterpret_cast<const h8*>(W1 + (16 * t + r) * DIN + 32 * s + 8 * q);
+            v = *reinterpret_cast<uint4*>(&a);
+        } else if (f < Lay::F_W3T) {
+            const int t = (f - Lay::F_W2) / 2, s = (f - Lay::F_W2) % 2;
+            h8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = W2[(16 * t + r) * H + 32 * s + k_chain(q, j)];
+            v = *reinterpret_cast<uint4*>(&a);
+        } else if (f < Lay::F_W2T) {
+            const int t = f - Lay::F_W3T;
+            b8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int o = k_load(q, j);
+                a[j] = (__bf16)(o < d_out ? (float)W3[o * H + 16 * t + r] : 0.0f);
+            }
+            v = *reinterpret_cast<uint4*>(&a);
+        } else if (f < Lay::F_W1T) {
+            const int t = (f - Lay::F_W2T) / 2, s = (f - Lay::F_W2T) % 2;
+            b8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = (__bf16)(float)W2[(32 * s + k_chain(q, j)) * H + 16 * t + r];
+            v = *reinterpret_cast<uint4*>(&a);
+        } else {
+            const int t = (f - Lay::F_W1T) / 2, s = (f - Lay::F_W1T) % 2;
+            b8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = (__bf16)(float)W1[(32 * s + k_chain(q, j)) * DIN + 16 * t + r];
+            v = *reinterpret_cast<uint4*>(&a);
+        }
+        frag[f * 64 + lane] = v;
+    }
+    __syncthreads();
+    auto fh = [&](int f) { uint4 u = frag[f * 64 + lane]; return *reinterpret_cast<h8*>(&u); };
+    auto fb = [&](int f) { uint4 u = frag[f * 64 + lane]; return *reinterpret_cast<b8*>(&u); };
+
+    short* S = reinterpret_cast<short*>(lds + Lay::FRAG_BYTES + wv * Lay::WAVE_BYTES);
+    // operand with 4 consecutive points (4q..4q+3) of one unit row
+    auto sread = [&](int row) { return *reinterpret_cast<const s4*>(S + row * kPts + 4 * q); };
+
+    f4 acc1[4][TIN], acc2[4][4], acc3[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        acc3[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < TIN; ++s) acc1[t][s] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc2[t][s] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    const int64_t per_iter = (int64_t)kBwdWaves * kPts;
+    const int64_t iters = (N + per_iter - 1) / per_iter;
+    for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        const int64_t base = it * per_iter + wv * kPts;
+        const int64_t p = base + r;
+        const bool valid = p < N;
+        // forward recompute
+        h8 xb[KS1];
+#pragma unroll
+        for (int s = 0; s < KS1; ++s)
+            xb[s] = valid ? *reinterpret_cast<const h8*>(x + p * DIN + 32 * s + 8 * q) : h8{};
+        h4 h1[4], h2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS1; ++s) c = mma_h(fh(Lay::F_W1 + t * KS1 + s), xb[s], c);
+            h1[t] = relu_h(c);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) c = mma_h(fh(Lay::F_W2 + 2 * t + s), cat_h(h1[2 * s], h1[2 * s + 1]), c);
+            h2[t] = relu_h(c);
+        }
+        // incoming gradient, loaded k order (outputs 8q..8q+7)
+        b8 dyb;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int o = k_load(q, j);
+            dyb[j] = (__bf16)((valid && o < d_out) ? d_y[p * d_out + o] : 0.0f);
+        }
+        // dH2 = W3^T dY, masked by the stored activation
+        f4 da2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f4 c = mma_b(fb(Lay::F_W3T + t), dyb, f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i] = (float)h2[t][i] > 0.0f ? (float)(__bf16)c[i] : 0.0f;
+            da2[t] = c;
+        }
+        // dH1 = W2^T dA2, masked
+        f4 da1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) c = mma_b(fb(Lay::F_W2T + 2 * t + s), cat_b(da2[2 * s], da2[2 * s + 1]), c);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i] = (float)h1[t][i] > 0.0f ? (float)(__bf16)c[i] : 0.0f;
+            da1[t] = c;
+        }
+        // dX = W1^T dA1
+        if (d_x) {
+#pragma unroll
+            for (int t = 0; t < TIN; ++t) {
+                f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 2; ++s) c = mma_b(fb(Lay::F_W1T + 2 * t + s), cat_b(da1[2 * s], da1[2 * s + 1]), c);
+                if (valid) *reinterpret_cast<f4*>(d_x + p * DIN + 16 * t + 4 * q) = c;
+            }
+        }
+        // transpose the weight-gradient operands through LDS: row = unit, column = point
+        if (q < 2) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) S[(Lay::R_DY + k_load(q, j)) * kPts + r] = __builtin_bit_cast(short, (__bf16)dyb[j]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * t + 4 * q + i;
+                S[(Lay::R_H2 + u) * kPts + r] = bf_bits((float)h2[t][i]);
+                S[(Lay::R_H1 + u) * kPts + r] = bf_bits((float)h1[t][i]);
+                S[(Lay::R_DA2 + u) * kPts + r] = bf_bits(da2[t][i]);
+                S[(Lay::R_DA1 + u) * kPts + r] = bf_bits(da1[t][i]);
+            }
+        // dW1's point-major input operand straight from memory (4 points per lane)
+        s4 xk[TIN];
+#pragma unroll
+        for (int s = 0; s < TIN; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t pp = base + 4 * q + i;
+                xk[s][i] = bf_bits(pp < N ? (float)x[pp * DIN + 16 * s + r] : 0.0f);
+            }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc3[t] = mma_b16(sread(Lay::R_DY + r), sread(Lay::R_H2 + 16 * t + r), acc3[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const s4 a = sread(Lay::R_DA2 + 16 * t + r);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc2[t][s] = mma_b16(a, sread(Lay::R_H1 + 16 * s + r), acc2[t][s]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const s4 a = sread(Lay::R_DA1 + 16 * t + r);
+#pragma unroll
+            for (int s = 0; s < TIN; ++s) acc1[t][s] = mma_b16(a, xk[s], acc1[t][s]);
+        }
+        __syncthreads();
+    }
+
+    // ---- reduce the four waves in a fixed order, then write this group's partial
+    float* P = reinterpret_cast<float*>(lds + Lay::FRAG_BYTES);
+    for (int w = 0; w < kBwdWaves; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * t + 4 * q + i;
+#pragma unroll
+                    for (int s = 0; s < TIN; ++s) {
+                        float& d = P[row * DIN + 16 * s + r];
+                        d = (w == 0 ? 0.0f : d) + acc1[t][s][i];
+                    }
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        float& d = P[H * DIN + row * H + 16 * s + r];
+                        d = (w == 0 ? 0.0f : d) + acc2[t][s][i];
+                    }
+                    float& d3 = P[H * DIN + H * H + (4 * q + i) * H + 16 * t + r];
+                    d3 = (w == 0 ? 0.0f : d3) + acc3[t][i];
+                }
+        }
+        __syncthreads();
+    }
+    float* out = partial + (size_t)blockIdx.x * Lay::PARTIAL;
+    for (int i = tid; i < Lay::PARTIAL; i += 256) out[i] = P[i];
+}
+
+// Sum the per-group partials in group order and scatter into dW1/dW2/dW3.
+template <int DIN>
+__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int groups, int d_out,
+                                                         float* __restrict__ dW1, float* __restrict__ dW2,
+                                                         float* __restrict__ dW3) {
+    constexpr int PARTIAL = BwdLayout<DIN>::PARTIAL;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= PARTIAL) return;
+    float s = 0.0f;
+    for (int g = 0; g < groups; ++g) s += partial[(size_t)g * PARTIAL + i];
+    if (i < H * DIN) {
+        dW1[i] = s;
+    } else if (i < H * DIN + H * H) {
+        dW2[i - H * DIN] = s;
+    } else {
+        const int k = i - H * DIN - H * H;
+        if (k / H < d_out) dW3[k] = s;
+    }
+}
+
+inline int bwd_groups(int64_t N) {
+    const int64_t per = (int64_t)kBwdWaves * kPts;
+    int64_t g = (N + per - 1) / per;
+    return (int)(g < kMaxBwdGroups ? (g > 0 ? g : 1) : kMaxBwdGroups);
+}
+
+template <int DIN>
+hipError_t fwd_impl(const MlpCall& c) {
+    int64_t tiles = (c.N + 15) / 16;
+    int64_t blocks = (tiles + 3) / 4;
+    const int64_t cap = 4096;
+    unsigned g = (unsigned)(blocks < cap ? (blocks > 0 ? blocks : 1) : cap);
+    mlp_fwd_kernel<DIN><<<g, 256, 0, c.stream>>>(c.N, (const _Float16*)c.x, (const _Float16*)c.W1,
+                                                 (const _Float16*)c.W2, (const _Float16*)c.W3, c.d_out, c.y);
+    return hipGetLastError();
+}
+
+template <int DIN>
+hipError_t bwd_impl(const MlpCall& c) {
+    using Lay = BwdLayout<DIN>;
+    const int g = bwd_groups(c.N);
+    float* part = (float*)c.workspace;
+    mlp_bwd_kernel<DIN><<<g, 256, Lay::LDS_BYTES, c.stream>>>(c.N, (const _Float16*)c.x, (const _Float16*)c.W1,
+                                                              (const _Float16*)c.W2, (const _Float16*)c.W3,
+                                                              c.d_out, c.d_y, c.d_x, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    mlp_reduce_kernel<DIN><<<(Lay::PARTIAL + 255) / 256, 256, 0, c.stream>>>(part, g, c.d_out, c.dW1, c.dW2, c.dW3);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int mlp_bwd_lds_bytes(int d_in) { return d_in == 32 ? BwdLayout<32>::LDS_BYTES : 0; }
+
+size_t mlp_bwd_workspace_bytes(int d_in, int, int, int64_t N) {
+    const size_t partial = (size_t)(H * d_in + H * H + 16 * H) * sizeof(float);
+    return partial * (size_t)bwd_groups(N);
+}
+
+hipError_t mlp_fwd(const MlpCall& c) {
+    switch (c.d_in) {
+        case 32: return fwd_impl<32>(c);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t mlp_bwd(const MlpCall& c) {
+    switch (c.d_in) {
+        case 32: return bwd_impl<32>(c);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace spx

@@ -1,0 +1,311 @@
+"""ctypes binding of libspx.so: the same entry points as include/spx.h.
+
+Argument marshalling only: every function checks that its tensors live on
+the GPU with the expected dtype and layout, passes raw pointers and the
+current HIP stream, and raises ``SpxError`` when the library returns a
+non-OK status.  All arithmetic happens in the library's kernels; if the
+library is missing, loading fails loudly (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspx.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "spx.h")
+
+SPX_OK, SPX_EINVAL, SPX_EALIGN, SPX_EUNSUPPORTED, SPX_EHIP = 0, 1, 2, 3, 4
+SPX_F32, SPX_F16 = 0, 1
+SPX_SIMPLEX, SPX_GRID = 0, 1
+MAX_DIMS, MAX_LEVELS = 6, 32
+
+
+class SpxError(RuntimeError):
+    def __init__(self, status: int, fn: str, detail: str):
+        super().__init__(f"{fn}: status {status} ({detail})")
+        self.status = status
+
+
+class spx_encoding(C.Structure):
+    _fields_ = [("n_dims", C.c_int32), ("n_levels", C.c_int32), ("log2_T", C.c_int32),
+                ("n_feat", C.c_int32), ("table_dtype", C.c_int32), ("cell", C.c_int32),
+                ("equal_memory", C.c_int32), ("res", C.c_int32 * MAX_LEVELS)]
+
+
+class spx_mlp(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("hidden", C.c_int32), ("d_out", C.c_int32)]
+
+
+_P = C.c_void_p
+_SIGNATURES = {
+    "spx_abi_version": (C.c_int32, []),
+    "spx_status_str": (C.c_char_p, [C.c_int]),
+    "spx_last_error": (C.c_char_p, []),
+    "spx_level_resolutions": (C.c_int, [C.c_double, C.c_double, C.c_int32, _P]),
+    "spx_level_scales": (C.c_int, [_P, _P]),
+    "spx_hash_primes": (C.c_int, [_P]),
+    "spx_encode_fwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, C.c_int32, _P]),
+    "spx_encode_bwd": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P]),
+    "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
+    "spx_cast_f32_f16": (C.c_int, [C.c_int64, _P, _P, _P]),
+    "spx_adam_step": (C.c_int, [C.c_int64, _P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
+                                C.c_float, C.c_int64, C.c_int32, _P]),
+    "spx_mse_grad": (C.c_int, [C.c_int64, _P, _P, _P, C.c_float, _P]),
+    "spx_mlp_fwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P]),
+    "spx_mlp_bwd_workspace": (C.c_int, [_P, C.c_int64, _P]),
+    "spx_mlp_bwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+}
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    """Load libspx.so (built by ``python -m paper_2311_15439_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_15439_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list:
+    """Names of the functions declared in include/spx.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(spx_\w+)\s*\(", text, re.M)))
+
+
+def _check(status: int, fn: str) -> None:
+    if status != SPX_OK:
+        raise SpxError(status, fn, lib().spx_last_error().decode())
+
+
+@dataclass
+class Encoding:
+    """Python view of spx_encoding.  ``res`` lists the level resolutions."""
+    n_dims: int
+    res: Sequence[int]
+    log2_T: int
+    n_feat: int = 2
+    table_dtype: int = SPX_F16
+    cell: int = SPX_SIMPLEX
+    equal_memory: bool = False
+    _c: spx_encoding = field(default=None, init=False, repr=False)
+
+    def __post_init__(self):
+        e = spx_encoding()
+        e.n_dims, e.n_levels, e.log2_T = self.n_dims, len(self.res), self.log2_T
+        e.n_feat, e.table_dtype, e.cell = self.n_feat, self.table_dtype, self.cell
+        e.equal_memory = int(self.equal_memory)
+        for i, r in enumerate(list(self.res)[:MAX_LEVELS]):
+            e.res[i] = int(r)
+        self._c = e
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.res)
+
+    @property
+    def n_vertices(self) -> int:
+        return (1 << self.n_dims) if self.cell == SPX_GRID else self.n_dims + 1
+
+    @property
+    def table_shape(self):
+        return (self.n_levels, 1 << self.log2_T, self.n_feat)
+
+    def ref(self):
+        return C.byref(self._c)
+
+
+# --------------------------------------------------------------- helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return SPX_F32
+    if t.dtype == torch.float16:
+        return SPX_F16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+# --------------------------------------------------------------- host helpers
+
+def spx_abi_version() -> int:
+    return int(lib().spx_abi_version())
+
+
+def spx_status_str(status: int) -> str:
+    return lib().spx_status_str(status).decode()
+
+
+def spx_last_error() -> str:
+    return lib().spx_last_error().decode()
+
+
+def spx_level_resolutions(n_min: float, growth: float, L: int):
+    out = (C.c_int32 * L)()
+    _check(lib().spx_level_resolutions(float(n_min), float(growth), L, C.cast(out, C.c_void_p)),
+           "spx_level_resolutions")
+    return [int(v) for v in out]
+
+
+def spx_level_scales(enc: Encoding):
+    out = (C.c_float * enc.n_levels)()
+    _check(lib().spx_level_scales(enc.ref(), C.cast(out, C.c_void_p)), "spx_level_scales")
+    return [float(v) for v in out]
+
+
+def spx_hash_primes():
+    out = (C.c_uint32 * MAX_DIMS)()
+    _check(lib().spx_hash_primes(C.cast(out, C.c_void_p)), "spx_hash_primes")
+    return [int(v) for v in out]
+
+
+# --------------------------------------------------------------- encoding
+
+def spx_encode_fwd(enc: Encoding, pts, tables, out, stream=None) -> None:
+    """pts [N, n] float32; tables [L, T, F]; out [N, L*F] float32/float16."""
+    torch = _torch()
+    N = pts.shape[0]
+    if pts.shape != (N, enc.n_dims) or tuple(tables.shape) != enc.table_shape:
+        raise ValueError("pts or tables shape does not match the encoding")
+    if tuple(out.shape) != (N, enc.n_levels * enc.n_feat):
+        raise ValueError("out shape must be [N, L*F]")
+    tdt = torch.float16 if enc.table_dtype == SPX_F16 else torch.float32
+    _check(lib().spx_encode_fwd(enc.ref(), N, _dev(pts, torch.float32, "pts"), _dev(tables, tdt, "tables"),
+                                _dev(out, None, "out"), _dtype_code(out), _stream(stream)), "spx_encode_fwd")
+
+
+def spx_encode_bwd(enc: Encoding, pts, d_out, d_tables, stream=None) -> None:
+    """Accumulates into d_tables [L, T, F] float32 (caller zeroes it)."""
+    torch = _torch()
+    N = pts.shape[0]
+    if pts.shape != (N, enc.n_dims) or tuple(d_tables.shape) != enc.table_shape:
+        raise ValueError("pts or d_tables shape does not match the encoding")
+    if tuple(d_out.shape) != (N, enc.n_levels * enc.n_feat):
+        raise ValueError("d_out shape must be [N, L*F]")
+    _check(lib().spx_encode_bwd(enc.ref(), N, _dev(pts, torch.float32, "pts"), _dev(d_out, None, "d_out"),
+                                _dtype_code(d_out), _dev(d_tables, torch.float32, "d_tables"), _stream(stream)),
+           "spx_encode_bwd")
+
+
+def spx_encode_debug(enc: Encoding, pts, idx=None, w=None, stream=None) -> None:
+    """idx [N, L, V] int32 (slots, reinterpret as uint32); w [N, L, V] float32."""
+    torch = _torch()
+    N = pts.shape[0]
+    shape = (N, enc.n_levels, enc.n_vertices)
+    if idx is not None and tuple(idx.shape) != shape:
+        raise ValueError("idx shape must be [N, L, V]")
+    if w is not None and tuple(w.shape) != shape:
+        raise ValueError("w shape must be [N, L, V]")
+    _check(lib().spx_encode_debug(enc.ref(), N, _dev(pts, torch.float32, "pts"),
+                                  None if idx is None else _dev(idx, torch.int32, "idx"),
+                                  None if w is None else _dev(w, torch.float32, "w"), _stream(stream)),
+           "spx_encode_debug")
+
+
+# --------------------------------------------------------------- elementwise
+
+def spx_cast_f32_f16(src, dst, stream=None) -> None:
+    torch = _torch()
+    if src.numel() != dst.numel():
+        raise ValueError("size mismatch")
+    _check(lib().spx_cast_f32_f16(src.numel(), _dev(src, torch.float32, "src"), _dev(dst, torch.float16, "dst"),
+                                  _stream(stream)), "spx_cast_f32_f16")
+
+
+def spx_adam_step(param, grad, m, v, param_f16=None, *, lr, beta1=0.9, beta2=0.99, eps=1e-15, step,
+                  zero_grad=False, stream=None) -> None:
+    torch = _torch()
+    n = param.numel()
+    for t in (grad, m, v) + ((param_f16,) if param_f16 is not None else ()):
+        if t.numel() != n:
+            raise ValueError("Adam state size mismatch")
+    _check(lib().spx_adam_step(n, _dev(param, torch.float32, "param"), _dev(grad, torch.float32, "grad"),
+                               _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"),
+                               None if param_f16 is None else _dev(param_f16, torch.float16, "param_f16"),
+                               float(lr), float(beta1), float(beta2), float(eps), int(step), int(bool(zero_grad)),
+                               _stream(stream)), "spx_adam_step")
+
+
+def spx_mse_grad(y, target, d_y, scale, stream=None) -> None:
+    torch = _torch()
+    n = y.numel()
+    if target.numel() != n or d_y.numel() != n:
+        raise ValueError("size mismatch")
+    f = torch.float32
+    _check(lib().spx_mse_grad(n, _dev(y, f, "y"), _dev(target, f, "target"), _dev(d_y, f, "d_y"), float(scale),
+                              _stream(stream)), "spx_mse_grad")
+
+
+# --------------------------------------------------------------- MLP
+
+def make_mlp(d_in: int = 32, hidden: int = 64, d_out: int = 3) -> spx_mlp:
+    m = spx_mlp()
+    m.d_in, m.hidden, m.d_out = d_in, hidden, d_out
+    return m
+
+
+def spx_mlp_fwd(mlp: spx_mlp, x, W1, W2, W3, y, stream=None) -> None:
+    torch = _torch()
+    N = x.shape[0]
+    if tuple(x.shape) != (N, mlp.d_in) or tuple(y.shape) != (N, mlp.d_out):
+        raise ValueError("x must be [N, d_in] and y [N, d_out]")
+    if (tuple(W1.shape) != (mlp.hidden, mlp.d_in) or tuple(W2.shape) != (mlp.hidden, mlp.hidden)
+            or tuple(W3.shape) != (mlp.d_out, mlp.hidden)):
+        raise ValueError("weight shapes do not match the network")
+    h = torch.float16
+    _check(lib().spx_mlp_fwd(C.byref(mlp), N, _dev(x, h, "x"), _dev(W1, h, "W1"), _dev(W2, h, "W2"),
+                             _dev(W3, h, "W3"), _dev(y, torch.float32, "y"), _stream(stream)), "spx_mlp_fwd")
+
+
+def spx_mlp_bwd_workspace(mlp: spx_mlp, N: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().spx_mlp_bwd_workspace(C.byref(mlp), N, C.byref(out)), "spx_mlp_bwd_workspace")
+    return int(out.value)
+
+
+def spx_mlp_bwd(mlp: spx_mlp, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, workspace, stream=None) -> None:
+    torch = _torch()
+    N = x.shape[0]
+    if tuple(d_y.shape) != (N, mlp.d_out):
+        raise ValueError("d_y must be [N, d_out]")
+    if d_x is not None and tuple(d_x.shape) != (N, mlp.d_in):
+        raise ValueError("d_x must be [N, d_in]")
+    h, f = torch.float16, torch.float32
+    _check(lib().spx_mlp_bwd(C.byref(mlp), N, _dev(x, h, "x"), _dev(W1, h, "W1"), _dev(W2, h, "W2"),
+                             _dev(W3, h, "W3"), _dev(d_y, f, "d_y"), None if d_x is None else _dev(d_x, f, "d_x"),
+                             _dev(dW1, f, "dW1"), _dev(dW2, f, "dW2"), _dev(dW3, f, "dW3"),
+                             _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)),
+           "spx_mlp_bwd")

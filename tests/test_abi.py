@@ -1,0 +1,108 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+the header declares, its host helpers agree bit for bit with the oracle's
+independently derived constants, and malformed calls are rejected on the
+host before anything is launched."""
+import ctypes as C
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_15439_amd import inputs, spx
+
+
+def test_exports_every_header_symbol():
+    names = spx.header_symbols()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", spx.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(spx.lib(), n)
+    assert set(names) == set(spx._SIGNATURES)
+
+
+def test_abi_version_and_status_strings():
+    assert spx.spx_abi_version() == 1
+    for s in range(5):
+        assert spx.spx_status_str(s).startswith("SPX_")
+
+
+def test_hash_primes_match_oracle():
+    assert spx.spx_hash_primes() == [int(p) for p in oracle.hash_primes()]
+
+
+@pytest.mark.parametrize("w", [inputs.PLAIN_2D, inputs.IMAGE_2D, inputs.VOLUME_3D] +
+                         [inputs.sweep_workload(n) for n in range(2, 7)])
+def test_level_resolutions_match_oracle(w):
+    ours = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
+    assert ours == list(oracle.level_resolutions(w.n_min, w.growth, w.n_levels))
+
+
+@pytest.mark.parametrize("n", range(1, 7))
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+@pytest.mark.parametrize("em", [False, True])
+def test_level_scales_match_oracle(n, cell, em):
+    res = [1, 2, 3, 16, 24, 36, 54, 100, 1000, 2048, 32768, 1 << 20]
+    enc = spx.Encoding(n, res, 14, cell=cell, equal_memory=em)
+    ours = np.array(spx.spx_level_scales(enc), np.float32)
+    theirs = oracle.level_scales(n, res, cell=cell, equal_memory=em and cell == spx.SPX_SIMPLEX)
+    np.testing.assert_array_equal(ours, theirs)
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_encode_argument_checks_on_host():
+    L = spx.lib()
+    good = spx.Encoding(3, [16, 32], 19)
+    fake = C.c_void_p(0x10000)  # never dereferenced: every call below fails its checks first
+    s = C.c_void_p(0)
+
+    def fwd(enc, N=10, pts=fake, tab=fake, out=fake, odt=spx.SPX_F32):
+        return L.spx_encode_fwd(enc.ref() if enc is not None else None, N, pts, tab, out, odt, s)
+
+    assert fwd(None) == spx.SPX_EINVAL
+    for bad in [dict(n_dims=0), dict(n_dims=7), dict(log2_T=0), dict(log2_T=27), dict(n_feat=3),
+                dict(table_dtype=5), dict(cell=2)]:
+        kw = dict(n_dims=3, res=[16, 32], log2_T=19)
+        kw.update(bad)
+        assert fwd(spx.Encoding(**kw)) == spx.SPX_EINVAL, bad
+    assert fwd(spx.Encoding(3, [16, 0], 19)) == spx.SPX_EINVAL
+    assert fwd(spx.Encoding(3, [], 19)) == spx.SPX_EINVAL
+    assert fwd(spx.Encoding(3, list(range(1, 34)), 19)) == spx.SPX_EINVAL
+    assert fwd(good, N=-1) == spx.SPX_EINVAL
+    assert fwd(good, pts=None) == spx.SPX_EINVAL
+    assert fwd(good, odt=7) == spx.SPX_EINVAL
+    assert fwd(good, out=None) == spx.SPX_EINVAL
+    assert fwd(good, pts=C.c_void_p(0x10002)) == spx.SPX_EALIGN
+    assert fwd(good, tab=C.c_void_p(0x10002)) == spx.SPX_EALIGN       # f16 F=2 rows are 4 bytes
+    assert fwd(good, out=C.c_void_p(0x10004)) == spx.SPX_EALIGN       # f32 F=2 rows are 8 bytes
+    assert "aligned" in spx.spx_last_error()
+    # N = 0 is a no-op that touches nothing
+    assert fwd(good, N=0, pts=None, tab=None, out=None) == spx.SPX_OK
+    assert L.spx_encode_bwd(good.ref(), 0, None, None, spx.SPX_F32, None, s) == spx.SPX_OK
+    assert L.spx_encode_bwd(good.ref(), 5, fake, fake, spx.SPX_F32, C.c_void_p(0x10001), s) == spx.SPX_EALIGN
+    assert L.spx_encode_debug(good.ref(), 5, fake, None, None, s) == spx.SPX_OK  # nothing requested
+
+
+def test_other_argument_checks_on_host():
+    L = spx.lib()
+    fake = C.c_void_p(0x10000)
+    s = C.c_void_p(0)
+    assert L.spx_cast_f32_f16(-1, fake, fake, s) == spx.SPX_EINVAL
+    assert L.spx_cast_f32_f16(0, None, None, s) == spx.SPX_OK
+    assert L.spx_adam_step(4, fake, fake, fake, fake, None, 1e-2, 0.9, 0.99, 1e-15, 0, 0, s) == spx.SPX_EINVAL
+    assert L.spx_adam_step(4, fake, fake, fake, fake, None, 1e-2, 1.0, 0.99, 1e-15, 1, 0, s) == spx.SPX_EINVAL
+    m = spx.make_mlp(32, 64, 3)
+    bad = spx.make_mlp(48, 64, 3)
+    size = C.c_size_t(0)
+    assert L.spx_mlp_bwd_workspace(C.byref(m), 1 << 20, C.byref(size)) == spx.SPX_OK and size.value > 0
+    assert L.spx_mlp_fwd(C.byref(bad), 10, fake, fake, fake, fake, fake, s) == spx.SPX_EUNSUPPORTED
+    assert L.spx_mlp_fwd(C.byref(spx.make_mlp(32, 64, 17)), 10, fake, fake, fake, fake, fake, s) == spx.SPX_EINVAL
+    assert L.spx_mlp_fwd(C.byref(m), 10, C.c_void_p(0x10008), fake, fake, fake, fake, s) == spx.SPX_EALIGN
+    assert L.spx_mlp_bwd(C.byref(m), 10, fake, fake, fake, fake, fake, None, fake, fake, fake, fake, 16, s) \
+        == spx.SPX_EINVAL  # workspace too small

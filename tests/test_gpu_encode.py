@@ -1,0 +1,239 @@
+"""GPU parity of the encoding kernels against the CPU oracle, through the C
+ABI.  Bars:
+  * hash slots and binary32 weights: bit-exact (same binary32 index path);
+  * forward features: |gpu - oracle| <= 1e-5 * sum_k |w_k t_k| (+ the
+    binary16 rounding of the output when it is stored in binary16);
+  * adjoint: per slot |gpu - oracle| <= (m + 2) * 2^-24 * sum |w d| where m
+    is the number of contributions to the slot (recursive summation bound);
+  * full-size workloads: sampled points, compared one by one with the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_15439_amd import inputs, spx
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _enc_pair(n, res, log2_T, F=2, f16=False, cell=spx.SPX_SIMPLEX, em=False):
+    g = spx.Encoding(n, list(res), log2_T, n_feat=F, table_dtype=spx.SPX_F16 if f16 else spx.SPX_F32,
+                     cell=cell, equal_memory=em)
+    o = oracle.Encoding(n, list(res), log2_T, n_feat=F, table_dtype=oracle.F16 if f16 else oracle.F32,
+                        cell=cell, equal_memory=em and cell == spx.SPX_SIMPLEX)
+    return g, o
+
+
+def _gpu_debug(enc, pts):
+    N = len(pts)
+    p = torch.from_numpy(pts).to(DEV)
+    idx = torch.empty((N, enc.n_levels, enc.n_vertices), dtype=torch.int32, device=DEV)
+    w = torch.empty((N, enc.n_levels, enc.n_vertices), dtype=torch.float32, device=DEV)
+    spx.spx_encode_debug(enc, p, idx, w)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy().view(np.uint32), w.cpu().numpy()
+
+
+def _gpu_fwd(enc, pts, tab, out_f16=False):
+    p = torch.from_numpy(pts).to(DEV)
+    t = torch.from_numpy(tab).to(DEV)
+    out = torch.empty((len(pts), enc.n_levels * enc.n_feat), device=DEV,
+                      dtype=torch.float16 if out_f16 else torch.float32)
+    spx.spx_encode_fwd(enc, p, t, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _gpu_bwd(enc, pts, d_out):
+    p = torch.from_numpy(pts).to(DEV)
+    d = torch.from_numpy(d_out).to(DEV)
+    g = torch.zeros(enc.table_shape, dtype=torch.float32, device=DEV)
+    spx.spx_encode_bwd(enc, p, d, g)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64)
+
+
+def _check_fwd(got, ref, mag, out_f16):
+    tol = 1e-5 * mag + 1e-30
+    if out_f16:
+        tol = tol + 2.0 ** -11 * np.abs(ref) + 2.0 ** -25
+    err = np.abs(got - ref)
+    bad = err > tol
+    assert not bad.any(), f"{bad.sum()} outputs out of tolerance; worst {err[bad].max()} vs tol {tol[bad].min()}"
+    return float((err / np.maximum(mag, 1e-30)).max())
+
+
+def _special_points(n, rng):
+    """Edge inputs: the cube's corners and faces, exact ties, points just
+    inside and outside the unit cube, and negative coordinates."""
+    rows = [np.zeros(n), np.ones(n), np.full(n, 0.5), np.full(n, np.float32(1) - np.float32(2 ** -24))]
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        rows.append(e)
+        rows.append(1.0 - e)
+    a = rng.random(n)
+    a[-1] = a[0]           # tie between the first and last axes
+    rows.append(a)
+    rows.append(-rng.random(n) * 0.3)   # negative coordinates (the hash is total)
+    rows.append(1.0 + rng.random(n) * 0.3)
+    return np.array(rows, np.float32)
+
+
+# ------------------------------------------------------------------ lookups
+
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_debug_bit_exact(n, cell):
+    rng = np.random.default_rng(100 + n)
+    res = [1, 2, 16, 37, 300, 4096, 1 << 15] if n <= 3 else [1, 3, 16, 61, 500]
+    g, o = _enc_pair(n, res, 19, cell=cell, em=(n % 2 == 0))
+    pts = np.concatenate([inputs.uniform_points(3001, n, 200 + n), _special_points(n, rng)])
+    idx, w = _gpu_debug(g, pts)
+    ref = oracle.encode_debug(o, pts)
+    np.testing.assert_array_equal(idx, ref["idx"])
+    np.testing.assert_array_equal(w.view(np.uint32), ref["w32"].view(np.uint32))
+
+
+# ------------------------------------------------------------------ forward
+
+FWD_CASES = [
+    # n, res, log2_T, F, table f16, out f16, cell
+    (2, [16, 24, 36, 54], 14, 2, False, False, spx.SPX_SIMPLEX),   # the plain 2-D configuration's shape
+    (2, [16, 24, 36, 54], 14, 2, False, False, spx.SPX_GRID),
+    (2, [16, 200, 3000, 32768], 22, 2, True, True, spx.SPX_SIMPLEX),
+    (3, [16, 64, 512, 2048], 19, 2, True, True, spx.SPX_SIMPLEX),
+    (3, [16, 64, 512, 2048], 19, 2, True, True, spx.SPX_GRID),
+    (3, [5, 50], 12, 1, False, True, spx.SPX_SIMPLEX),
+    (4, [16, 90], 16, 4, True, False, spx.SPX_SIMPLEX),
+    (5, [16, 90], 16, 8, False, False, spx.SPX_SIMPLEX),
+    (6, [7, 40], 20, 2, True, True, spx.SPX_SIMPLEX),
+    (6, [7, 40], 20, 2, True, True, spx.SPX_GRID),
+    (1, [9, 1000], 10, 2, False, False, spx.SPX_SIMPLEX),
+]
+
+
+@pytest.mark.parametrize("case", FWD_CASES, ids=lambda c: f"n{c[0]}F{c[3]}{'h' if c[4] else 'f'}{'h' if c[5] else 'f'}c{c[6]}")
+def test_fwd_parity(case):
+    n, res, log2_T, F, tf16, of16, cell = case
+    rng = np.random.default_rng(7)
+    g, o = _enc_pair(n, res, log2_T, F, tf16, cell)
+    pts = np.concatenate([inputs.uniform_points(4999, n, 300 + n), _special_points(n, rng)])
+    tab = inputs.tables(len(res), 1 << log2_T, F, 1.0, 400 + n, tf16)
+    got = _gpu_fwd(g, pts, tab, of16)
+    ref = oracle.encode_fwd(o, pts, tab)
+    mag = oracle.encode_fwd_absmag(o, pts, tab)
+    worst = _check_fwd(got, ref, mag, of16)
+    print(f"max |gpu-oracle| / sum|w t| = {worst:.3e}")
+
+
+def test_fwd_deterministic_and_edge_sizes():
+    g, o = _enc_pair(3, [16, 100], 16, 2, True)
+    tab = inputs.tables(2, 1 << 16, 2, 1.0, 5, True)
+    for N in [1, 63, 64, 65, 255, 256, 257, 1000]:
+        pts = inputs.uniform_points(N, 3, N)
+        a = _gpu_fwd(g, pts, tab)
+        b = _gpu_fwd(g, pts, tab)
+        np.testing.assert_array_equal(a, b)
+        _check_fwd(a, oracle.encode_fwd(o, pts, tab), oracle.encode_fwd_absmag(o, pts, tab), False)
+    # N = 0 is a no-op
+    p = torch.empty((0, 3), device=DEV)
+    out = torch.empty((0, 4), device=DEV)
+    spx.spx_encode_fwd(g, p, torch.from_numpy(tab).to(DEV), out)
+
+
+def test_fwd_max_level_count_and_table_size():
+    """32 levels, the largest level count, and a 2^24-entry table."""
+    res = list(oracle.level_resolutions(2, 1.4, 32))
+    g, o = _enc_pair(2, res, 16, 1, True)
+    tab = inputs.tables(32, 1 << 16, 1, 1.0, 9, True)
+    pts = inputs.uniform_points(2000, 2, 10)
+    _check_fwd(_gpu_fwd(g, pts, tab), oracle.encode_fwd(o, pts, tab), oracle.encode_fwd_absmag(o, pts, tab), False)
+    g, o = _enc_pair(3, [64, 4096], 24, 1, True)
+    tab = inputs.tables(2, 1 << 24, 1, 1.0, 11, True)
+    pts = inputs.uniform_points(2000, 3, 12)
+    _check_fwd(_gpu_fwd(g, pts, tab), oracle.encode_fwd(o, pts, tab), oracle.encode_fwd_absmag(o, pts, tab), False)
+
+
+# ------------------------------------------------------------------ adjoint
+
+BWD_CASES = [
+    (2, [16, 24, 36, 54], 14, 2, False, spx.SPX_SIMPLEX),
+    (2, [16, 24, 36, 54], 14, 2, True, spx.SPX_GRID),
+    (3, [4, 30, 512], 12, 2, False, spx.SPX_SIMPLEX),   # heavy contention at the coarse level
+    (3, [4, 30, 512], 12, 2, True, spx.SPX_GRID),
+    (4, [10, 80], 16, 4, False, spx.SPX_SIMPLEX),
+    (6, [5, 17], 18, 1, True, spx.SPX_SIMPLEX),
+    (1, [9, 100], 10, 8, False, spx.SPX_SIMPLEX),
+]
+
+
+@pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"n{c[0]}F{c[3]}{'h' if c[4] else 'f'}c{c[5]}")
+def test_bwd_parity(case):
+    n, res, log2_T, F, dout_f16, cell = case
+    g, o = _enc_pair(n, res, log2_T, F, False, cell)
+    pts = inputs.uniform_points(6001, n, 500 + n)
+    d = inputs.gradients(len(pts), len(res) * F, 600 + n)
+    if dout_f16:
+        d = d.astype(np.float16)
+    got = _gpu_bwd(g, pts, d)
+    ref, mag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
+    tol = (cnt + 2) * 2.0 ** -24 * mag + 1e-30
+    err = np.abs(got - ref)
+    assert (err <= tol).all(), f"worst {err.max()} ; {int((err > tol).sum())} slots out of tolerance"
+    assert np.all(got[cnt == 0] == 0)
+
+
+def test_bwd_dot_product_identity():
+    """<d, J t> = <J^T d, t> with both sides computed on the GPU."""
+    g, _ = _enc_pair(3, [16, 64, 256, 1024], 16, 2, True)
+    pts = inputs.uniform_points(20000, 3, 3)
+    tab = inputs.tables(4, 1 << 16, 2, 1.0, 4, True)
+    d = inputs.gradients(len(pts), 8, 5)
+    fwd = _gpu_fwd(g, pts, tab)
+    grad = _gpu_bwd(g, pts, d)
+    lhs = (d.astype(np.float64) * fwd).sum()
+    rhs = (grad * tab.astype(np.float64)).sum()
+    scale = (np.abs(d) * np.abs(fwd)).sum()
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def _full_size_workload(w, cell=spx.SPX_SIMPLEX, n_sample=2048):
+    res = oracle.level_resolutions(w.n_min, w.growth, w.n_levels)
+    g, o = _enc_pair(w.n_dims, res, w.log2_T, w.n_feat, w.table_f16, cell)
+    if w.n_dims == 3 and w.name.startswith("volume"):
+        pts = inputs.ray_points(w.n_points // 256, 256, w.seed_points)
+    elif w.name.startswith("image"):
+        pts = inputs.pixel_points(w.n_points, w.seed_points)
+    else:
+        pts = inputs.uniform_points(w.n_points, w.n_dims, w.seed_points)
+    tab = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, w.table_f16)
+    got = _gpu_fwd(g, pts, tab, out_f16=True)
+    sel = np.random.default_rng(1).choice(len(pts), n_sample, replace=False)
+    ref = oracle.encode_fwd(o, pts[sel], tab)
+    mag = oracle.encode_fwd_absmag(o, pts[sel], tab)
+    _check_fwd(got[sel], ref, mag, True)
+    # adjoint at full size: d_out nonzero only on the sampled points, so the
+    # oracle's sum over those points is the whole gradient
+    d = np.zeros((len(pts), w.n_levels * w.n_feat), np.float16)
+    d[sel] = inputs.gradients(n_sample, w.n_levels * w.n_feat, 2).astype(np.float16)
+    gg = _gpu_bwd(g, pts, d)
+    ref, mag, cnt = oracle.encode_bwd(o, pts[sel], d[sel].astype(np.float64), with_stats=True)
+    tol = (cnt + 2) * 2.0 ** -24 * mag + 1e-30
+    assert (np.abs(gg - ref) <= tol).all()
+
+
+@pytest.mark.parametrize("w", [inputs.IMAGE_2D, inputs.VOLUME_3D], ids=lambda w: w.name.split()[0])
+def test_full_size_workloads(w):
+    _full_size_workload(w)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+def test_full_size_dimension_sweep(n, cell):
+    _full_size_workload(inputs.sweep_workload(n), cell, n_sample=1024)

@@ -32,6 +32,8 @@ MUTANTS = {
                          "h2[o] = f16r(s);\n            a2[o] = sa;"),
     "mlp bwd mask": ("dh1[i] = orc_round_bf16(h1[i] > 0.0 ? s : 0.0);", "dh1[i] = orc_round_bf16(s);"),
     "f16 rounding": ("double q = nearbyint(ldexp(a, 10 - e));", "double q = floor(ldexp(a, 10 - e));"),
+    "mse sign": ("d_y[i] = scale * ((double)y[i] - (double)target[i]);",
+                 "d_y[i] = scale * ((double)target[i] - (double)y[i]);"),
     "adam bias correction": ("double mhat = mi / bc1, vhat = vi / bc2;", "double mhat = mi, vhat = vi / bc2;"),
 }
 

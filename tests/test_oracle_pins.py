@@ -520,3 +520,13 @@ def test_adam_matches_torch():
         opt.step()
         p, m, v, _ = oracle.adam_step(p, g, m, v, 1e-2, 0.9, 0.99, 1e-15, step)
     np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-5, atol=1e-6)
+
+
+def test_mse_grad_matches_autograd():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(8)
+    y = rng.normal(size=(100, 3)).astype(np.float32)
+    tgt = rng.random((100, 3)).astype(np.float32)
+    ty = torch.tensor(y.astype(np.float64), requires_grad=True)
+    torch.nn.functional.mse_loss(ty, torch.tensor(tgt.astype(np.float64))).backward()
+    np.testing.assert_allclose(oracle.mse_grad(y, tgt, 2.0 / y.size), ty.grad.numpy(), rtol=1e-15)
