@@ -136,11 +136,49 @@ spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, 
  *   d_out      device [N][L*F] of d_out_dtype (SPX_F32 or SPX_F16), aligned
  *              to F * element size (at most 16 bytes).
  *   d_tables   device [L][T][F] binary32, 4-byte aligned.  ACCUMULATED: the
- *              caller zeroes it.  Floating-point atomics make the summation
- *              order, and so the last bits, vary from run to run.
+ *              caller zeroes it.  The summation order, and so the last bits,
+ *              vary from run to run.
+ *   workspace  NULL: every contribution is added with a binary32 atomic.
+ *              Otherwise device memory of at least the size returned by
+ *              spx_encode_bwd_workspace(), 256-byte aligned: contributions
+ *              are first binned by slot range and summed in LDS, and each
+ *              slot of d_tables is then updated by exactly one workgroup
+ *              (no global atomics; much faster for large batches).
+ *              workspace_bytes is its size.  Its contents on entry are
+ *              ignored and on return undefined.
  */
 spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
-                          int32_t d_out_dtype, float* d_tables, hipStream_t stream);
+                          int32_t d_out_dtype, float* d_tables, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+/*
+ * Workspace bytes the binned adjoint needs for N points (written to
+ * *bytes): about N * L * V records of 8 to 64 bytes plus per-bucket
+ * counters.  SPX_EUNSUPPORTED if the configuration cannot be binned (use the
+ * atomic path, workspace NULL).
+ */
+spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* bytes);
+
+/*
+ * Adjoint and optimizer in one pass: the table gradient of spx_encode_bwd
+ * (as if accumulated into a zeroed table) is summed per slot in LDS and the
+ * Adam step of spx_adam_step is applied to every entry of the tables at
+ * once, so no gradient table is written or read.  Every entry is updated
+ * (entries with zero gradient still decay m and v), exactly as
+ * spx_encode_bwd into zeros followed by spx_adam_step over all L*T*F
+ * entries.
+ *   param, m, v  device [L][T][F] binary32, 16-byte aligned: master tables
+ *                and Adam moments, updated in place.
+ *   param_f16    device [L][T][F] binary16, 8-byte aligned, or NULL: receives
+ *                the binary16 image of the updated tables (the forward's
+ *                input).
+ *   lr, beta1, beta2, eps, step   as spx_adam_step.
+ *   workspace    as spx_encode_bwd (required here), 256-byte aligned.
+ */
+spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                               int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
+                               float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream);
 
 /*
  * Lookup introspection for parity tests: the slot and the binary32 weight

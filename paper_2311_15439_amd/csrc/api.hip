@@ -167,8 +167,21 @@ spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, 
     return from_hip(run(enc, c), "spx_encode_fwd launch");
 }
 
+spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* bytes) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if (N < 0) return fail(SPX_EINVAL, "N < 0");
+    if (!bytes) return fail(SPX_EINVAL, "bytes is NULL");
+    spx::BinLayout lay = spx::bin_layout(enc->n_dims, enc->n_feat, enc->n_levels, enc->log2_T, N,
+                                         enc->cell == SPX_SIMPLEX);
+    if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
+    *bytes = lay.total_bytes;
+    return SPX_OK;
+}
+
 spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
-                          int32_t d_out_dtype, float* d_tables, hipStream_t stream) {
+                          int32_t d_out_dtype, float* d_tables, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream) {
     spx_status st = check_encoding(enc);
     if (st) return st;
     if ((st = check_points(N, pts))) return st;
@@ -180,10 +193,63 @@ spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, 
     if (!aligned(d_tables, 4)) return fail(SPX_EALIGN, "d_tables not 4-byte aligned");
     spx::EncodeCall c = base_call(enc, N, pts, stream);
     c.op = spx::EncodeOp::Adjoint;
+    if (workspace) {
+        spx::BinLayout lay = spx::bin_layout(enc->n_dims, enc->n_feat, enc->n_levels, enc->log2_T, N,
+                                             enc->cell == SPX_SIMPLEX);
+        if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
+        if (workspace_bytes < lay.total_bytes)
+            return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", lay.total_bytes, workspace_bytes);
+        if (!aligned(workspace, 256)) return fail(SPX_EALIGN, "workspace not 256-byte aligned");
+        c.op = spx::EncodeOp::AdjointBinned;
+        c.workspace = workspace;
+    }
     c.dout_f16 = d_out_dtype == SPX_F16;
     c.d_out = d_out;
     c.d_tables = d_tables;
     return from_hip(run(enc, c), "spx_encode_bwd launch");
+}
+
+spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                               int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
+                               float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (d_out_dtype != SPX_F32 && d_out_dtype != SPX_F16) return fail(SPX_EINVAL, "d_out_dtype=%d", d_out_dtype);
+    if (step < 1) return fail(SPX_EINVAL, "step=%lld < 1", (long long)step);
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return fail(SPX_EINVAL, "beta1/beta2 must lie in [0,1) and eps >= 0");
+    if (!param || !m || !v) return fail(SPX_EINVAL, "param, m or v is NULL");
+    if (!aligned(param, 16) || !aligned(m, 16) || !aligned(v, 16) || (param_f16 && !aligned(param_f16, 8)))
+        return fail(SPX_EALIGN, "Adam state misaligned (param/m/v 16 bytes, param_f16 8 bytes)");
+    if (N > 0 && !d_out) return fail(SPX_EINVAL, "d_out is NULL");
+    const int ge = d_out_dtype == SPX_F16 ? 2 : 4;
+    if (d_out && !aligned(d_out, row_align(enc->n_feat, ge))) return fail(SPX_EALIGN, "d_out not row-aligned");
+    spx::BinLayout lay = spx::bin_layout(enc->n_dims, enc->n_feat, enc->n_levels, enc->log2_T, N,
+                                         enc->cell == SPX_SIMPLEX);
+    if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
+    if (!workspace || workspace_bytes < lay.total_bytes)
+        return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", lay.total_bytes, workspace_bytes);
+    if (!aligned(workspace, 256)) return fail(SPX_EALIGN, "workspace not 256-byte aligned");
+    if (lay.groups != 1)
+        return fail(SPX_EUNSUPPORTED, "fused Adam needs all levels in one group (%d groups here)", lay.groups);
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::AdjointBinned;
+    c.workspace = workspace;
+    c.dout_f16 = d_out_dtype == SPX_F16;
+    c.d_out = d_out;
+    c.adam.param = param;
+    c.adam.m = m;
+    c.adam.v = v;
+    c.adam.param_f16 = param_f16;
+    c.adam.lr = lr;
+    c.adam.b1 = beta1;
+    c.adam.b2 = beta2;
+    c.adam.eps = eps;
+    c.adam.inv_bc1 = 1.0f / (float)(1.0 - pow((double)beta1, (double)step));
+    c.adam.inv_bc2 = 1.0f / (float)(1.0 - pow((double)beta2, (double)step));
+    return from_hip(run(enc, c), "spx_encode_bwd_adam launch");
 }
 
 spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts, uint32_t* idx, float* w,

@@ -1,0 +1,273 @@
+// Binned adjoint of the encoding: the gradient scatter without global
+// atomics.
+//
+// On MI355X a scattered binary32 atomic costs one L2 request per lane (about
+// four times a scattered store), and atomics that pile onto one line
+// serialise; the coarse levels of a multiresolution table send thousands of
+// updates to each slot.  This path therefore sorts the contributions by slot
+// range first and sums them in LDS:
+//   count    every (point, level, vertex) contribution is assigned a bucket
+//            (level, slot >> s); each workgroup counts its contributions per
+//            bucket in LDS and writes its row of counts;
+//   colscan  per bucket, exclusive prefix over workgroups, plus the bucket
+//            total;
+//   scan     exclusive prefix over bucket totals: where each bucket's
+//            records start;
+//   scatter  each workgroup recomputes its points' lookups and writes one
+//            record {slot within the bucket, w * d_out[F]} per contribution
+//            into its reserved range of the bucket (LDS cursors);
+//   accum    one workgroup per bucket adds its records into an LDS copy of
+//            the bucket's 2^s slots, then adds that slice to d_tables with
+//            coalesced read-modify-write (each slot is owned by exactly one
+//            workgroup) -- or, in the fused variant, applies the Adam step
+//            to the slice directly, so no gradient table is stored at all.
+// Levels are processed in groups when the bucket count or the record count
+// of all levels together would not fit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "encode_kernels.hpp"
+
+namespace spx {
+
+constexpr int kBinBlock = 256;
+
+// One record per contribution: slot within the bucket and the F values,
+// padded to a power of two so that a record is one aligned store.
+template <int F>
+struct alignas(F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64) BinRec {
+    uint32_t slot;
+    float v[F];
+};
+
+// Per-workgroup contiguous range of points.
+__device__ __forceinline__ void bin_chunk(int64_t N, int64_t chunk, int64_t& lo, int64_t& hi) {
+    lo = (int64_t)blockIdx.x * chunk;
+    hi = lo + chunk < N ? lo + chunk : N;
+}
+
+template <class Tag, int D>
+__global__ __launch_bounds__(kBinBlock) void bin_count_kernel(int64_t N, const float* __restrict__ pts, LevelArgs lv,
+                                                              BinPlan plan) {
+    extern __shared__ uint32_t hist[];
+    for (int b = threadIdx.x; b < plan.B; b += kBinBlock) hist[b] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    bin_chunk(N, plan.chunk, lo, hi);
+    for (int64_t pt = lo + threadIdx.x; pt < hi; pt += kBinBlock) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        for (int l = plan.l0; l < plan.l1; ++l) {
+            const uint32_t bl = (uint32_t)(l - plan.l0) * plan.bpl;
+            visit_level(Tag{}, y, lv.sigma[l], lv.mask, [&](const auto& h, const auto& w, int) {
+                constexpr int K = sizeof(w) / sizeof(float);
+#pragma unroll
+                for (int k = 0; k < K; ++k) atomicAdd(&hist[bl + (h[k] >> plan.s_log2)], 1u);
+            });
+        }
+    }
+    __syncthreads();
+    uint32_t* row = plan.counts + (size_t)blockIdx.x * plan.B;
+    for (int b = threadIdx.x; b < plan.B; b += kBinBlock) row[b] = hist[b];
+}
+
+// Per bucket: exclusive prefix of the counts over workgroups, and the total.
+// A block handles 64 buckets; 16 threads per bucket each sum a contiguous
+// segment of workgroups, the 16 segment sums are scanned in LDS, and each
+// thread then rewrites its segment as an exclusive prefix.
+constexpr int kColBuckets = 64, kColSegs = 16;
+static __global__ __launch_bounds__(kColBuckets * kColSegs) void bin_colscan_kernel(BinPlan plan,
+                                                                                  uint32_t* __restrict__ totals) {
+    __shared__ uint32_t seg[kColSegs][kColBuckets];
+    const int lb = threadIdx.x % kColBuckets, sg = threadIdx.x / kColBuckets;
+    const int b = blockIdx.x * kColBuckets + lb;
+    const int per = (plan.W + kColSegs - 1) / kColSegs;
+    const int w0 = sg * per, w1 = w0 + per < plan.W ? w0 + per : plan.W;
+    uint32_t s = 0;
+    if (b < plan.B)
+        for (int w = w0; w < w1; ++w) s += plan.counts[(size_t)w * plan.B + b];
+    seg[sg][lb] = s;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int k = 0; k < sg; ++k) run += seg[k][lb];
+    if (b < plan.B) {
+        for (int w = w0; w < w1; ++w) {
+            uint32_t* c = plan.counts + (size_t)w * plan.B + b;
+            const uint32_t v = *c;
+            *c = run;
+            run += v;
+        }
+        if (sg == kColSegs - 1) totals[b] = run;
+    }
+}
+
+// Exclusive scan of the bucket totals by one workgroup: base[b], base[B].
+static __global__ __launch_bounds__(1024) void bin_scan_kernel(int B, const uint32_t* __restrict__ totals,
+                                                        uint32_t* __restrict__ base) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (B + 1023) / 1024;
+    const int b0 = t * per, b1 = b0 + per < B ? b0 + per : B;
+    uint32_t s = 0;
+    for (int b = b0; b < b1; ++b) s += totals[b];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan of the 1024 partial sums
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? part[t - 1] : 0u;
+    for (int b = b0; b < b1; ++b) {
+        base[b] = run;
+        run += totals[b];
+    }
+    if (t == 1023) base[B] = part[1023];
+}
+
+template <class Tag, int D, int F, typename GT>
+__global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(int64_t N, const float* __restrict__ pts,
+                                                                const GT* __restrict__ d_out, LevelArgs lv,
+                                                                BinPlan plan) {
+    extern __shared__ uint32_t cursor[];
+    const uint32_t* row = plan.counts + (size_t)blockIdx.x * plan.B;
+    for (int b = threadIdx.x; b < plan.B; b += kBinBlock) cursor[b] = plan.base[b] + row[b];
+    __syncthreads();
+    BinRec<F>* __restrict__ recs = reinterpret_cast<BinRec<F>*>(plan.recs);
+    const uint32_t smask = (1u << plan.s_log2) - 1u;
+    int64_t lo, hi;
+    bin_chunk(N, plan.chunk, lo, hi);
+    for (int64_t pt = lo + threadIdx.x; pt < hi; pt += kBinBlock) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        const GT* __restrict__ grow = d_out + pt * (int64_t)(lv.L * F);
+        for (int l = plan.l0; l < plan.l1; ++l) {
+            float g[F];
+            RowIO<GT, F>::load(grow + l * F, g);
+            const uint32_t bl = (uint32_t)(l - plan.l0) * plan.bpl;
+            visit_level(Tag{}, y, lv.sigma[l], lv.mask, [&](const auto& h, const auto& w, int) {
+                constexpr int K = sizeof(w) / sizeof(float);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t pos = atomicAdd(&cursor[bl + (h[k] >> plan.s_log2)], 1u);
+                    BinRec<F> r;
+                    r.slot = h[k] & smask;
+#pragma unroll
+                    for (int j = 0; j < F; ++j) r.v[j] = w[k] * g[j];
+                    recs[pos] = r;
+                }
+            });
+        }
+    }
+}
+
+constexpr int kAccBlock = 512;
+constexpr int kAccUnroll = 4;
+
+template <int F, bool ADAM>
+__global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint32_t T, float* __restrict__ d_tables,
+                                                              AdamArgs adam) {
+    extern __shared__ float acc[];
+    const int S = 1 << plan.s_log2;
+    for (int i = threadIdx.x; i < S * F; i += kAccBlock) acc[i] = 0.0f;
+    __syncthreads();
+    const int b = blockIdx.x;
+    const BinRec<F>* __restrict__ recs = reinterpret_cast<const BinRec<F>*>(plan.recs);
+    const uint32_t r0 = plan.base[b], r1 = plan.base[b + 1];
+    uint32_t r = r0 + threadIdx.x;
+    // several records in flight per thread before their LDS adds
+    for (; r + (kAccUnroll - 1) * kAccBlock < r1; r += kAccUnroll * kAccBlock) {
+        BinRec<F> rec[kAccUnroll];
+#pragma unroll
+        for (int u = 0; u < kAccUnroll; ++u) rec[u] = recs[r + u * kAccBlock];
+#pragma unroll
+        for (int u = 0; u < kAccUnroll; ++u)
+#pragma unroll
+            for (int j = 0; j < F; ++j) atomicAdd(&acc[rec[u].slot * F + j], rec[u].v[j]);
+    }
+    for (; r < r1; r += kAccBlock) {
+        const BinRec<F> rec = recs[r];
+#pragma unroll
+        for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], rec.v[j]);
+    }
+    __syncthreads();
+    const int l = plan.l0 + b / plan.bpl;
+    const size_t off = ((size_t)l * T + (size_t)(b % plan.bpl) * S) * F;
+    const int n4 = S * F / 4;  // S * F is a multiple of 4 whenever S >= 4
+    const float* base_ptr = ADAM ? adam.param : d_tables;
+    if (n4 * 4 == S * F && ((uintptr_t)(base_ptr + off) & 15) == 0) {
+        for (int i = threadIdx.x; i < n4; i += kAccBlock) {
+            const f32x4 g = reinterpret_cast<const f32x4*>(acc)[i];
+            if constexpr (!ADAM) {
+                f32x4* out = reinterpret_cast<f32x4*>(d_tables + off) + i;
+                *out = *out + g;
+            } else {
+                f32x4* P = reinterpret_cast<f32x4*>(adam.param + off) + i;
+                f32x4* M = reinterpret_cast<f32x4*>(adam.m + off) + i;
+                f32x4* Vv = reinterpret_cast<f32x4*>(adam.v + off) + i;
+                f32x4 p = *P, m = *M, v = *Vv;
+                f16x4 h;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    m[q] = adam.b1 * m[q] + (1.0f - adam.b1) * g[q];
+                    v[q] = adam.b2 * v[q] + (1.0f - adam.b2) * g[q] * g[q];
+                    p[q] = p[q] - adam.lr * (m[q] * adam.inv_bc1) / (sqrtf(v[q] * adam.inv_bc2) + adam.eps);
+                    h[q] = (f16)p[q];
+                }
+                *P = p;
+                *M = m;
+                *Vv = v;
+                if (adam.param_f16) reinterpret_cast<f16x4*>((f16*)adam.param_f16 + off)[i] = h;
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < S * F; i += kAccBlock) {
+            const float g = acc[i];
+            if constexpr (!ADAM) {
+                d_tables[off + i] += g;
+            } else {
+                const float m = adam.b1 * adam.m[off + i] + (1.0f - adam.b1) * g;
+                const float v = adam.b2 * adam.v[off + i] + (1.0f - adam.b2) * g * g;
+                const float p = adam.param[off + i] - adam.lr * (m * adam.inv_bc1) / (sqrtf(v * adam.inv_bc2) + adam.eps);
+                adam.m[off + i] = m;
+                adam.v[off + i] = v;
+                adam.param[off + i] = p;
+                if (adam.param_f16) ((f16*)adam.param_f16)[off + i] = (f16)p;
+            }
+        }
+    }
+}
+
+template <class Tag, int D, int F, typename GT>
+hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
+    const GT* d_out = (const GT*)c.d_out;
+    bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
+    bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
+    bin_scan_kernel<<<1, 1024, 0, c.stream>>>(p.B, totals, p.base);
+    bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv, p);
+    const size_t lds = (size_t)(F << p.s_log2) * sizeof(float);
+    if (c.adam.param)
+        bin_accum_kernel<F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, nullptr, c.adam);
+    else
+        bin_accum_kernel<F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, c.d_tables, c.adam);
+    return hipGetLastError();
+}
+
+template <class Tag, int D, int F>
+hipError_t binned_adjoint(const EncodeCall& c) {
+    BinLayout lay = bin_layout(c.D, c.F, c.lv.L, 31 - __builtin_clz(c.lv.mask + 1u), c.N, Tag::simplex);
+    char* ws = (char*)c.workspace;
+    for (int g = 0; g < lay.groups; ++g) {
+        BinPlan p = bin_plan(lay, g, ws);
+        uint32_t* totals = (uint32_t*)(ws + lay.off_totals);
+        hipError_t e = c.dout_f16 ? binned_adjoint_group<Tag, D, F, f16>(c, p, totals)
+                                  : binned_adjoint_group<Tag, D, F, float>(c, p, totals);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace spx

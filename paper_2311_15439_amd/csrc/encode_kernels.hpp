@@ -215,65 +215,4 @@ __global__ __launch_bounds__(kBlock) void encode_debug_kernel(int64_t N, const f
     }
 }
 
-// ---- dispatch -------------------------------------------------------------
-
-inline unsigned grid_for(int64_t N) {
-    int64_t blocks = (N + kBlock - 1) / kBlock;
-    const int64_t cap = 1 << 20;
-    return (unsigned)(blocks < cap ? (blocks > 0 ? blocks : 1) : cap);
-}
-
-template <class Tag, int D, int F>
-hipError_t fwd_dispatch_types(const EncodeCall& c) {
-    dim3 g(grid_for(c.N)), b(kBlock);
-    if (c.table_f16 && c.out_f16)
-        encode_fwd_kernel<Tag, D, F, f16, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (f16*)c.out, c.lv);
-    else if (c.table_f16)
-        encode_fwd_kernel<Tag, D, F, f16, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (float*)c.out, c.lv);
-    else if (c.out_f16)
-        encode_fwd_kernel<Tag, D, F, float, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (f16*)c.out, c.lv);
-    else
-        encode_fwd_kernel<Tag, D, F, float, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (float*)c.out, c.lv);
-    return hipGetLastError();
-}
-
-template <class Tag, int D, int F>
-hipError_t bwd_dispatch_types(const EncodeCall& c) {
-    dim3 g(grid_for(c.N)), b(kBlock);
-    if (c.dout_f16)
-        encode_bwd_kernel<Tag, D, F, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.d_out, c.d_tables, c.lv);
-    else
-        encode_bwd_kernel<Tag, D, F, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.d_out, c.d_tables, c.lv);
-    return hipGetLastError();
-}
-
-template <class Tag, int D>
-hipError_t dispatch_F(const EncodeCall& c) {
-    if (c.op == EncodeOp::Debug) {
-        encode_debug_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, c.idx, c.w, c.lv);
-        return hipGetLastError();
-    }
-    const bool fwd = c.op == EncodeOp::Forward;
-    switch (c.F) {
-        case 1: return fwd ? fwd_dispatch_types<Tag, D, 1>(c) : bwd_dispatch_types<Tag, D, 1>(c);
-        case 2: return fwd ? fwd_dispatch_types<Tag, D, 2>(c) : bwd_dispatch_types<Tag, D, 2>(c);
-        case 4: return fwd ? fwd_dispatch_types<Tag, D, 4>(c) : bwd_dispatch_types<Tag, D, 4>(c);
-        case 8: return fwd ? fwd_dispatch_types<Tag, D, 8>(c) : bwd_dispatch_types<Tag, D, 8>(c);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <class Tag>
-hipError_t dispatch_D(const EncodeCall& c) {
-    switch (c.D) {
-        case 1: return dispatch_F<Tag, 1>(c);
-        case 2: return dispatch_F<Tag, 2>(c);
-        case 3: return dispatch_F<Tag, 3>(c);
-        case 4: return dispatch_F<Tag, 4>(c);
-        case 5: return dispatch_F<Tag, 5>(c);
-        case 6: return dispatch_F<Tag, 6>(c);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 }  // namespace spx

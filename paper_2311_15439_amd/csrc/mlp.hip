@@ -130,7 +130,7 @@ __device__ __forceinline__ short bf_bits(float v) { return __builtin_bit_cast(sh
 
 constexpr int kBwdWaves = 4;
 constexpr int kPts = 16;  // points per wave per iteration
-constexpr int kMaxBwdGroups = 512;
+constexpr int kMaxBwdGroups = 256;
 
 template <int DIN>
 struct BwdLayout {
@@ -355,16 +355,27 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
     for (int i = tid; i < Lay::PARTIAL; i += 256) out[i] = P[i];
 }
 
-// Sum the per-group partials in group order and scatter into dW1/dW2/dW3.
+// Sum the per-group partials and scatter into dW1/dW2/dW3.  A block owns 64
+// outputs; its four thread groups each sum a contiguous quarter of the
+// groups, and the quarters are added in order, so the result does not depend
+// on scheduling.
 template <int DIN>
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int groups, int d_out,
                                                          float* __restrict__ dW1, float* __restrict__ dW2,
                                                          float* __restrict__ dW3) {
     constexpr int PARTIAL = BwdLayout<DIN>::PARTIAL;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= PARTIAL) return;
+    __shared__ float part[4][64];
+    const int o = threadIdx.x & 63, qd = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + o;
+    const int per = (groups + 3) / 4;
+    const int g0 = qd * per, g1 = g0 + per < groups ? g0 + per : groups;
     float s = 0.0f;
-    for (int g = 0; g < groups; ++g) s += partial[(size_t)g * PARTIAL + i];
+    if (i < PARTIAL)
+        for (int g = g0; g < g1; ++g) s += partial[(size_t)g * PARTIAL + i];
+    part[qd][o] = s;
+    __syncthreads();
+    if (qd != 0 || i >= PARTIAL) return;
+    s = ((part[0][o] + part[1][o]) + part[2][o]) + part[3][o];
     if (i < H * DIN) {
         dW1[i] = s;
     } else if (i < H * DIN + H * H) {
@@ -402,7 +413,7 @@ hipError_t bwd_impl(const MlpCall& c) {
                                                               c.d_out, c.d_y, c.d_x, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    mlp_reduce_kernel<DIN><<<(Lay::PARTIAL + 255) / 256, 256, 0, c.stream>>>(part, g, c.d_out, c.dW1, c.dW2, c.dW3);
+    mlp_reduce_kernel<DIN><<<(Lay::PARTIAL + 63) / 64, 256, 0, c.stream>>>(part, g, c.d_out, c.dW1, c.dW2, c.dW3);
     return hipGetLastError();
 }
 

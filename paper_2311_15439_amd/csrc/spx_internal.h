@@ -18,7 +18,99 @@ struct LevelArgs {
     int32_t L;        // number of levels
 };
 
-enum class EncodeOp { Forward, Adjoint, Debug };
+// Adam hyper-parameters and state for the fused adjoint + optimizer path
+// (param == nullptr: plain adjoint into d_tables).
+struct AdamArgs {
+    float* param;
+    float* m;
+    float* v;
+    void* param_f16;  // binary16 image of param, or nullptr
+    float lr, b1, b2, eps, inv_bc1, inv_bc2;
+};
+
+enum class EncodeOp { Forward, Adjoint, AdjointBinned, Debug };
+
+// Binned adjoint: one level group's plan (device pointers into the caller's
+// workspace).
+struct BinPlan {
+    int l0, l1;       // levels [l0, l1) of this group
+    int s_log2;       // slots per bucket = 2^s_log2
+    int bpl;          // buckets per level
+    int B;            // buckets in this group
+    int W;            // workgroups of the count and scatter passes
+    int64_t chunk;    // points per workgroup
+    uint32_t* counts;  // [W][B]
+    uint32_t* base;    // [B + 1]
+    void* recs;        // records
+};
+
+// Sizes shared by every group; a pure function of the encoding and N so the
+// workspace query and the launch agree.
+struct BinLayout {
+    int L, lpg, groups, s_log2, bpl, Bmax, W, rec_bytes, V;
+    int64_t N, chunk;
+    size_t off_counts, off_base, off_totals, off_recs, total_bytes;
+    bool ok;
+};
+
+inline size_t bin_align(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simplex) {
+    BinLayout b{};
+    b.L = L;
+    b.N = N;
+    b.V = simplex ? D + 1 : (1 << D);
+    b.rec_bytes = F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64;
+    const int lf = F == 1 ? 0 : F == 2 ? 1 : F == 4 ? 2 : 3;
+    // bucket of 2^s slots: its binary32 accumulator (2^s * F * 4 bytes) is
+    // 64 KiB, or 128 KiB when needed to keep at most 16384 buckets per level
+    int s = 14 - lf;
+    if (log2T - s > 14) s = 15 - lf;
+    if (s > log2T) s = log2T;
+    b.s_log2 = s;
+    b.bpl = 1 << (log2T - s);
+    b.ok = b.bpl <= 16384 && N >= 0;
+    // levels per group: at most 16384 buckets, fewer than 2^31 records, and
+    // at most 1 GiB of records (only the per-point load repeats per group)
+    int lpg = 16384 / b.bpl;
+    if (lpg > L) lpg = L;
+    const double per_level = (double)N * b.V;
+    while (lpg > 1 && (per_level * lpg >= 2147483647.0 || per_level * lpg * b.rec_bytes > 1073741824.0)) --lpg;
+    if (per_level * lpg >= 2147483647.0) b.ok = false;
+    if (lpg < 1) { lpg = 1; b.ok = false; }
+    b.lpg = lpg;
+    b.groups = (L + lpg - 1) / lpg;
+    b.Bmax = lpg * b.bpl;
+    int64_t W = (N + 255) / 256;
+    b.W = (int)(W < 512 ? (W > 0 ? W : 1) : 512);
+    b.chunk = (N + b.W - 1) / b.W;
+    size_t off = 0;
+    b.off_counts = off;
+    off = bin_align(off + (size_t)b.W * b.Bmax * 4);
+    b.off_base = off;
+    off = bin_align(off + ((size_t)b.Bmax + 1) * 4);
+    b.off_totals = off;
+    off = bin_align(off + (size_t)b.Bmax * 4);
+    b.off_recs = off;
+    off = bin_align(off + (size_t)N * lpg * b.V * b.rec_bytes);
+    b.total_bytes = off;
+    return b;
+}
+
+inline BinPlan bin_plan(const BinLayout& lay, int g, char* ws) {
+    BinPlan p;
+    p.l0 = g * lay.lpg;
+    p.l1 = p.l0 + lay.lpg < lay.L ? p.l0 + lay.lpg : lay.L;
+    p.s_log2 = lay.s_log2;
+    p.bpl = lay.bpl;
+    p.B = (p.l1 - p.l0) * lay.bpl;
+    p.W = lay.W;
+    p.chunk = lay.chunk;
+    p.counts = (uint32_t*)(ws + lay.off_counts);
+    p.base = (uint32_t*)(ws + lay.off_base);
+    p.recs = ws + lay.off_recs;
+    return p;
+}
 
 struct EncodeCall {
     EncodeOp op;
@@ -32,6 +124,8 @@ struct EncodeCall {
     float* d_tables;
     uint32_t* idx;
     float* w;
+    void* workspace;  // binned adjoint only
+    AdamArgs adam;    // binned adjoint only
     LevelArgs lv;
     hipStream_t stream;
 };

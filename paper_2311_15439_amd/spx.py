@@ -49,7 +49,10 @@ _SIGNATURES = {
     "spx_level_scales": (C.c_int, [_P, _P]),
     "spx_hash_primes": (C.c_int, [_P]),
     "spx_encode_fwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, C.c_int32, _P]),
-    "spx_encode_bwd": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P]),
+    "spx_encode_bwd": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P, C.c_size_t, _P]),
+    "spx_encode_bwd_workspace": (C.c_int, [_P, C.c_int64, _P]),
+    "spx_encode_bwd_adam": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_float, C.c_float,
+                                      C.c_float, C.c_float, C.c_int64, _P, C.c_size_t, _P]),
     "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_cast_f32_f16": (C.c_int, [C.c_int64, _P, _P, _P]),
     "spx_adam_step": (C.c_int, [C.c_int64, _P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
@@ -207,17 +210,46 @@ def spx_encode_fwd(enc: Encoding, pts, tables, out, stream=None) -> None:
                                 _dev(out, None, "out"), _dtype_code(out), _stream(stream)), "spx_encode_fwd")
 
 
-def spx_encode_bwd(enc: Encoding, pts, d_out, d_tables, stream=None) -> None:
-    """Accumulates into d_tables [L, T, F] float32 (caller zeroes it)."""
+def spx_encode_bwd_workspace(enc: Encoding, N: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().spx_encode_bwd_workspace(enc.ref(), N, C.byref(out)), "spx_encode_bwd_workspace")
+    return int(out.value)
+
+
+def spx_encode_bwd(enc: Encoding, pts, d_out, d_tables, workspace=None, stream=None) -> None:
+    """Accumulates into d_tables [L, T, F] float32 (caller zeroes it).  With a
+    uint8 GPU ``workspace`` of spx_encode_bwd_workspace() bytes the binned
+    path runs; without one, the atomic path."""
     torch = _torch()
     N = pts.shape[0]
     if pts.shape != (N, enc.n_dims) or tuple(d_tables.shape) != enc.table_shape:
         raise ValueError("pts or d_tables shape does not match the encoding")
     if tuple(d_out.shape) != (N, enc.n_levels * enc.n_feat):
         raise ValueError("d_out shape must be [N, L*F]")
+    ws = None if workspace is None else _dev(workspace, torch.uint8, "workspace")
+    nbytes = 0 if workspace is None else workspace.numel()
     _check(lib().spx_encode_bwd(enc.ref(), N, _dev(pts, torch.float32, "pts"), _dev(d_out, None, "d_out"),
-                                _dtype_code(d_out), _dev(d_tables, torch.float32, "d_tables"), _stream(stream)),
-           "spx_encode_bwd")
+                                _dtype_code(d_out), _dev(d_tables, torch.float32, "d_tables"), ws, nbytes,
+                                _stream(stream)), "spx_encode_bwd")
+
+
+def spx_encode_bwd_adam(enc: Encoding, pts, d_out, param, m, v, param_f16=None, *, lr, beta1=0.9, beta2=0.99,
+                        eps=1e-15, step, workspace, stream=None) -> None:
+    """Adjoint + Adam on the tables in one pass (no gradient table)."""
+    torch = _torch()
+    N = pts.shape[0]
+    for t in (param, m, v) + ((param_f16,) if param_f16 is not None else ()):
+        if tuple(t.shape) != enc.table_shape:
+            raise ValueError("table state shape does not match the encoding")
+    if tuple(d_out.shape) != (N, enc.n_levels * enc.n_feat):
+        raise ValueError("d_out shape must be [N, L*F]")
+    f = torch.float32
+    _check(lib().spx_encode_bwd_adam(enc.ref(), N, _dev(pts, f, "pts"), _dev(d_out, None, "d_out"), _dtype_code(d_out),
+                                     _dev(param, f, "param"), _dev(m, f, "m"), _dev(v, f, "v"),
+                                     None if param_f16 is None else _dev(param_f16, torch.float16, "param_f16"),
+                                     float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                     _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)),
+           "spx_encode_bwd_adam")
 
 
 def spx_encode_debug(enc: Encoding, pts, idx=None, w=None, stream=None) -> None:

@@ -84,8 +84,13 @@ def test_encode_argument_checks_on_host():
     assert "aligned" in spx.spx_last_error()
     # N = 0 is a no-op that touches nothing
     assert fwd(good, N=0, pts=None, tab=None, out=None) == spx.SPX_OK
-    assert L.spx_encode_bwd(good.ref(), 0, None, None, spx.SPX_F32, None, s) == spx.SPX_OK
-    assert L.spx_encode_bwd(good.ref(), 5, fake, fake, spx.SPX_F32, C.c_void_p(0x10001), s) == spx.SPX_EALIGN
+    assert L.spx_encode_bwd(good.ref(), 0, None, None, spx.SPX_F32, None, None, 0, s) == spx.SPX_OK
+    assert L.spx_encode_bwd(good.ref(), 5, fake, fake, spx.SPX_F32, C.c_void_p(0x10001), None, 0, s) == spx.SPX_EALIGN
+    need = spx.spx_encode_bwd_workspace(good, 5)
+    assert need > 0
+    assert L.spx_encode_bwd(good.ref(), 5, fake, fake, spx.SPX_F32, fake, fake, need - 1, s) == spx.SPX_EINVAL
+    assert L.spx_encode_bwd(good.ref(), 5, fake, fake, spx.SPX_F32, fake, C.c_void_p(0x10010), need, s) \
+        == spx.SPX_EALIGN
     assert L.spx_encode_debug(good.ref(), 5, fake, None, None, s) == spx.SPX_OK  # nothing requested
 
 
@@ -106,3 +111,17 @@ def test_other_argument_checks_on_host():
     assert L.spx_mlp_fwd(C.byref(m), 10, C.c_void_p(0x10008), fake, fake, fake, fake, s) == spx.SPX_EALIGN
     assert L.spx_mlp_bwd(C.byref(m), 10, fake, fake, fake, fake, fake, None, fake, fake, fake, fake, 16, s) \
         == spx.SPX_EINVAL  # workspace too small
+
+
+def test_binned_workspace_sizes():
+    """The binned adjoint's workspace: records for every contribution plus
+    counters; bigger for more points and more vertices."""
+    e2 = spx.Encoding(2, [16] * 16, 22)
+    a = spx.spx_encode_bwd_workspace(e2, 1 << 20)
+    assert a >= (1 << 20) * 16 * 3 * 16  # one 16-byte record per (point, level, vertex)
+    assert spx.spx_encode_bwd_workspace(e2, 1 << 10) < a
+    g3 = spx.Encoding(3, [16] * 16, 19, cell=spx.SPX_GRID)
+    s3 = spx.Encoding(3, [16] * 16, 19)
+    assert spx.spx_encode_bwd_workspace(g3, 1 << 16) > spx.spx_encode_bwd_workspace(s3, 1 << 16)
+    # the largest table still bins (one level per group)
+    assert spx.spx_encode_bwd_workspace(spx.Encoding(6, [16] * 32, 26, n_feat=8), 1 << 16) > 0

@@ -49,11 +49,14 @@ def _gpu_fwd(enc, pts, tab, out_f16=False):
     return out.cpu().numpy().astype(np.float64)
 
 
-def _gpu_bwd(enc, pts, d_out):
+def _gpu_bwd(enc, pts, d_out, binned=False):
     p = torch.from_numpy(pts).to(DEV)
     d = torch.from_numpy(d_out).to(DEV)
     g = torch.zeros(enc.table_shape, dtype=torch.float32, device=DEV)
-    spx.spx_encode_bwd(enc, p, d, g)
+    ws = None
+    if binned:
+        ws = torch.empty(spx.spx_encode_bwd_workspace(enc, len(pts)), dtype=torch.uint8, device=DEV)
+    spx.spx_encode_bwd(enc, p, d, g, ws)
     torch.cuda.synchronize()
     return g.cpu().numpy().astype(np.float64)
 
@@ -173,15 +176,23 @@ BWD_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"n{c[0]}F{c[3]}{'h' if c[4] else 'f'}c{c[5]}")
-def test_bwd_parity(case):
+BWD_CASES += [
+    (6, [3, 5, 9, 12] * 4, 14, 2, False, spx.SPX_GRID),   # 64 vertices: the binned path runs two level groups
+    (3, [16, 64], 24, 8, True, spx.SPX_SIMPLEX),          # 2^24-entry tables, 8 features
+]
+
+
+@pytest.mark.parametrize("binned", [False, True], ids=["atomic", "binned"])
+@pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"n{c[0]}L{len(c[1])}F{c[3]}{'h' if c[4] else 'f'}c{c[5]}")
+def test_bwd_parity(case, binned):
     n, res, log2_T, F, dout_f16, cell = case
     g, o = _enc_pair(n, res, log2_T, F, False, cell)
-    pts = inputs.uniform_points(6001, n, 500 + n)
+    N = (1 << 17) + 3 if n == 6 and cell == spx.SPX_GRID else 6001
+    pts = inputs.uniform_points(N, n, 500 + n)
     d = inputs.gradients(len(pts), len(res) * F, 600 + n)
     if dout_f16:
         d = d.astype(np.float16)
-    got = _gpu_bwd(g, pts, d)
+    got = _gpu_bwd(g, pts, d, binned)
     ref, mag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
     tol = (cnt + n + 2) * 2.0 ** -24 * mag + 1e-30
     err = np.abs(got - ref)
@@ -189,14 +200,15 @@ def test_bwd_parity(case):
     assert np.all(got[cnt == 0] == 0)
 
 
-def test_bwd_dot_product_identity():
+@pytest.mark.parametrize("binned", [False, True], ids=["atomic", "binned"])
+def test_bwd_dot_product_identity(binned):
     """<d, J t> = <J^T d, t> with both sides computed on the GPU."""
     g, _ = _enc_pair(3, [16, 64, 256, 1024], 16, 2, True)
     pts = inputs.uniform_points(20000, 3, 3)
     tab = inputs.tables(4, 1 << 16, 2, 1.0, 4, True)
     d = inputs.gradients(len(pts), 8, 5)
     fwd = _gpu_fwd(g, pts, tab)
-    grad = _gpu_bwd(g, pts, d)
+    grad = _gpu_bwd(g, pts, d, binned)
     lhs = (d.astype(np.float64) * fwd).sum()
     rhs = (grad * tab.astype(np.float64)).sum()
     scale = (np.abs(d) * np.abs(fwd)).sum()
@@ -224,7 +236,7 @@ def _full_size_workload(w, cell=spx.SPX_SIMPLEX, n_sample=2048):
     # oracle's sum over those points is the whole gradient
     d = np.zeros((len(pts), w.n_levels * w.n_feat), np.float16)
     d[sel] = inputs.gradients(n_sample, w.n_levels * w.n_feat, 2).astype(np.float16)
-    gg = _gpu_bwd(g, pts, d)
+    gg = _gpu_bwd(g, pts, d, binned=True)
     ref, mag, cnt = oracle.encode_bwd(o, pts[sel], d[sel].astype(np.float64), with_stats=True)
     tol = (cnt + w.n_dims + 2) * 2.0 ** -24 * mag + 1e-30
     err = np.abs(gg - ref)
@@ -240,3 +252,65 @@ def test_full_size_workloads(w):
 @pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
 def test_full_size_dimension_sweep(n, cell):
     _full_size_workload(inputs.sweep_workload(n), cell, n_sample=1024)
+
+
+def test_binned_equals_atomic_on_the_image_workload():
+    """Both adjoint paths at the image workload's full size agree slot by slot
+    to the summation-order bound (the count per slot is taken from the
+    binned path's own input: every point contributes to every level)."""
+    w = inputs.IMAGE_2D
+    res = oracle.level_resolutions(w.n_min, w.growth, w.n_levels)
+    g, _ = _enc_pair(2, res, w.log2_T, 2, True)
+    pts = inputs.pixel_points(w.n_points, 77)
+    d = inputs.gradients(w.n_points, 32, 78)
+    a = _gpu_bwd(g, pts, d, binned=False)
+    b = _gpu_bwd(g, pts, d, binned=True)
+    # |sum| differences are bounded by 2 (m + 3) u sum|w d|; bound sum|w d| by the
+    # total |d| mass per level, a loose but order-independent scale
+    scale = np.abs(d.astype(np.float64)).reshape(-1, 16, 2).sum(0)  # [L, F]
+    assert np.all(np.abs(a - b) <= 2.0 ** -24 * (w.n_points * 3 + 8) * scale[:, None, :] + 1e-30)
+
+
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+def test_bwd_adam_fused_parity(cell):
+    """Adjoint + Adam in one pass against the oracle's adjoint followed by
+    its Adam step.  The GPU's gradient differs from the oracle's by the
+    summation bound tolg; that error is carried through the Adam update
+    (d m / d g = 1 - b1, d v / d g = 2 (1 - b2) g), on top of the binary32
+    roundings of the step itself."""
+    n, res, log2_T, F = 3, [4, 16, 64, 200], 13, 2
+    g, o = _enc_pair(n, res, log2_T, F, True, cell)
+    pts = inputs.uniform_points(20001, n, 31)
+    d = inputs.gradients(len(pts), len(res) * F, 32) * 1e-3
+    shape = g.table_shape
+    rng = np.random.default_rng(33)
+    p0 = (rng.normal(size=shape) * 1e-2).astype(np.float32)
+    m0 = (rng.normal(size=shape) * 1e-3).astype(np.float32)
+    v0 = (rng.random(shape) * 1e-5 + 1e-7).astype(np.float32)
+    f32 = lambda x: float(np.float32(x))
+    lr, b1, b2, eps, step = f32(1e-2), f32(0.9), f32(0.99), f32(1e-15), 5
+    tp, tm, tv = (torch.from_numpy(a.copy()).to(DEV) for a in (p0, m0, v0))
+    th = torch.empty(shape, dtype=torch.float16, device=DEV)
+    ws = torch.empty(spx.spx_encode_bwd_workspace(g, len(pts)), dtype=torch.uint8, device=DEV)
+    spx.spx_encode_bwd_adam(g, torch.from_numpy(pts).to(DEV), torch.from_numpy(d).to(DEV), tp, tm, tv, th,
+                            lr=lr, beta1=b1, beta2=b2, eps=eps, step=step, workspace=ws)
+    torch.cuda.synchronize()
+    gref, gmag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
+    tolg = (cnt + n + 2) * 2.0 ** -24 * gmag + 1e-30
+    p, m, v, _ = oracle.adam_step(p0.ravel(), gref.ravel().astype(np.float32), m0.ravel(), v0.ravel(),
+                                  lr, b1, b2, eps, step)
+    gp, gm, gv = (t.cpu().numpy().ravel().astype(np.float64) for t in (tp, tm, tv))
+    u = 2.0 ** -24
+    G, TG = np.abs(gref.ravel()), tolg.ravel() + u * np.abs(gref.ravel())  # + rounding gref to binary32
+    tol_m = 3 * u * (b1 * np.abs(m0.ravel()) + (1 - b1) * G) + (1 - b1) * TG
+    tol_v = 4 * u * (b2 * v0.ravel() + (1 - b2) * G ** 2) + (1 - b2) * (2 * G + TG) * TG
+    bc1, bc2 = 1 - b1 ** step, 1 - b2 ** step
+    sv = np.sqrt(np.maximum(v.astype(np.float64) - tol_v, 0) / bc2) + eps
+    upd = np.abs(p0.ravel().astype(np.float64) - p)
+    tol_p = (2 * u * np.abs(p) + 10 * u * upd + lr * (tol_m / bc1) / sv
+             + upd * 0.5 * (tol_v / bc2) / (sv * sv))
+    for name, got, ref, tol in [("m", gm, m, tol_m), ("v", gv, v, tol_v), ("p", gp, p, tol_p)]:
+        err = np.abs(got - ref)
+        assert (err <= tol).all(), f"{name}: worst err/tol {np.max(err / tol):.3f}"
+    np.testing.assert_array_equal(th.cpu().numpy().view(np.uint16).ravel(),
+                                  oracle.cast_f32_f16(gp.astype(np.float32)))
