@@ -74,6 +74,7 @@ spx::LevelArgs level_args(const spx_encoding* e) {
     level_scales(e, lv.sigma);
     const int n = e->n_dims;
     lv.Fn = (float)((sqrt((double)n + 1.0) - 1.0) / (double)n);
+    lv.reach = e->cell == SPX_SIMPLEX ? (float)sqrt((double)n + 1.0) : 1.0f;
     lv.mask = (uint32_t)((1ull << e->log2_T) - 1ull);
     lv.L = e->n_levels;
     return lv;
@@ -90,6 +91,12 @@ spx::EncodeCall base_call(const spx_encoding* e, int64_t N, const float* pts, hi
     c.lv = level_args(e);
     c.stream = s;
     return c;
+}
+
+spx::BinLayout layout_for(const spx_encoding* e, int64_t N) {
+    const spx::LevelArgs lv = level_args(e);
+    return spx::bin_layout(e->n_dims, e->n_feat, e->n_levels, e->log2_T, N, e->cell == SPX_SIMPLEX, lv.sigma,
+                           (double)lv.reach);
 }
 
 hipError_t run(const spx_encoding* e, const spx::EncodeCall& c) {
@@ -172,8 +179,7 @@ spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* 
     if (st) return st;
     if (N < 0) return fail(SPX_EINVAL, "N < 0");
     if (!bytes) return fail(SPX_EINVAL, "bytes is NULL");
-    spx::BinLayout lay = spx::bin_layout(enc->n_dims, enc->n_feat, enc->n_levels, enc->log2_T, N,
-                                         enc->cell == SPX_SIMPLEX);
+    spx::BinLayout lay = layout_for(enc, N);
     if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
     *bytes = lay.total_bytes;
     return SPX_OK;
@@ -194,8 +200,7 @@ spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, 
     spx::EncodeCall c = base_call(enc, N, pts, stream);
     c.op = spx::EncodeOp::Adjoint;
     if (workspace) {
-        spx::BinLayout lay = spx::bin_layout(enc->n_dims, enc->n_feat, enc->n_levels, enc->log2_T, N,
-                                             enc->cell == SPX_SIMPLEX);
+        spx::BinLayout lay = layout_for(enc, N);
         if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
         if (workspace_bytes < lay.total_bytes)
             return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", lay.total_bytes, workspace_bytes);
@@ -226,8 +231,7 @@ spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* 
     if (N > 0 && !d_out) return fail(SPX_EINVAL, "d_out is NULL");
     const int ge = d_out_dtype == SPX_F16 ? 2 : 4;
     if (d_out && !aligned(d_out, row_align(enc->n_feat, ge))) return fail(SPX_EALIGN, "d_out not row-aligned");
-    spx::BinLayout lay = spx::bin_layout(enc->n_dims, enc->n_feat, enc->n_levels, enc->log2_T, N,
-                                         enc->cell == SPX_SIMPLEX);
+    spx::BinLayout lay = layout_for(enc, N);
     if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
     if (!workspace || workspace_bytes < lay.total_bytes)
         return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", lay.total_bytes, workspace_bytes);

@@ -48,6 +48,33 @@ __device__ __forceinline__ void bin_chunk(int64_t N, int64_t chunk, int64_t& lo,
     hi = lo + chunk < N ? lo + chunk : N;
 }
 
+// Is the cell (corner c, all vertices c + {0,1}^n) inside level l's dense
+// box?  If so, write the dense index of its corner and the per-axis strides.
+template <int D>
+__device__ __forceinline__ bool dense_cell(const BinPlan& plan, int l, const int32_t (&c)[D], int32_t& e0,
+                                           int32_t (&stride)[D]) {
+    const int ext = plan.ext[l];
+    bool in = true;
+    int32_t e = plan.doff[l], st = 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        in = in && c[i] >= 0 && c[i] <= ext - 2;
+        e += c[i] * st;
+        stride[i] = st;
+        st *= ext;
+    }
+    e0 = e;
+    return in;
+}
+
+template <int D>
+__device__ __forceinline__ int32_t dense_vertex(int32_t e0, const int32_t (&stride)[D], uint32_t offs) {
+    int32_t e = e0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) e += ((offs >> i) & 1u) ? stride[i] : 0;
+    return e;
+}
+
 template <class Tag, int D>
 __global__ __launch_bounds__(kBinBlock) void bin_count_kernel(int64_t N, const float* __restrict__ pts, LevelArgs lv,
                                                               BinPlan plan) {
@@ -61,8 +88,11 @@ __global__ __launch_bounds__(kBinBlock) void bin_count_kernel(int64_t N, const f
         load_point<Tag, D>(pts, pt, lv.Fn, y);
         for (int l = plan.l0; l < plan.l1; ++l) {
             const uint32_t bl = (uint32_t)(l - plan.l0) * plan.bpl;
-            visit_level(Tag{}, y, lv.sigma[l], lv.mask, [&](const auto& h, const auto& w, int) {
+            visit_level_ex(Tag{}, y, lv.sigma[l], lv.mask,
+                           [&](const auto& h, const auto& w, int, const auto& cell, const auto&) {
                 constexpr int K = sizeof(w) / sizeof(float);
+                int32_t e0, stride[D];
+                if (l < plan.P && dense_cell<D>(plan, l, cell, e0, stride)) return;  // summed in LDS instead
 #pragma unroll
                 for (int k = 0; k < K; ++k) atomicAdd(&hist[bl + (h[k] >> plan.s_log2)], 1u);
             });
@@ -148,8 +178,11 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(int64_t N, const
             float g[F];
             RowIO<GT, F>::load(grow + l * F, g);
             const uint32_t bl = (uint32_t)(l - plan.l0) * plan.bpl;
-            visit_level(Tag{}, y, lv.sigma[l], lv.mask, [&](const auto& h, const auto& w, int) {
+            visit_level_ex(Tag{}, y, lv.sigma[l], lv.mask,
+                           [&](const auto& h, const auto& w, int, const auto& cell, const auto&) {
                 constexpr int K = sizeof(w) / sizeof(float);
+                int32_t e0, stride[D];
+                if (l < plan.P && dense_cell<D>(plan, l, cell, e0, stride)) return;  // summed in LDS instead
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const uint32_t pos = atomicAdd(&cursor[bl + (h[k] >> plan.s_log2)], 1u);
@@ -164,17 +197,132 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(int64_t N, const
     }
 }
 
+// Privatised coarse levels: each workgroup sums its points' contributions
+// from in-box cells into a dense LDS array, then stores it as its partial.
+template <class Tag, int D, int F, typename GT>
+__global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const float* __restrict__ pts,
+                                                               const GT* __restrict__ d_out, LevelArgs lv,
+                                                               BinPlan plan) {
+    extern __shared__ float dacc[];
+    const int n = plan.Dtot * F;
+    for (int i = threadIdx.x; i < n; i += kBinBlock) dacc[i] = 0.0f;
+    __syncthreads();
+    int64_t lo, hi;
+    bin_chunk(N, plan.chunk, lo, hi);
+    for (int64_t pt = lo + threadIdx.x; pt < hi; pt += kBinBlock) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        const GT* __restrict__ grow = d_out + pt * (int64_t)(lv.L * F);
+        for (int l = 0; l < plan.P; ++l) {
+            float g[F];
+            RowIO<GT, F>::load(grow + l * F, g);
+            visit_level_ex(Tag{}, y, lv.sigma[l], lv.mask,
+                           [&](const auto& h, const auto& w, int, const auto& cell, const auto& offs) {
+                constexpr int K = sizeof(w) / sizeof(float);
+                int32_t e0, stride[D];
+                if (!dense_cell<D>(plan, l, cell, e0, stride)) return;  // emitted as records instead
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int32_t e = dense_vertex<D>(e0, stride, offs[k]);
+#pragma unroll
+                    for (int j = 0; j < F; ++j) atomicAdd(&dacc[e * F + j], w[k] * g[j]);
+                }
+            });
+        }
+    }
+    __syncthreads();
+    float* __restrict__ out = plan.partial + (size_t)blockIdx.x * n;
+    for (int i = threadIdx.x; i < n; i += kBinBlock) out[i] = dacc[i];
+}
+
+// Sum of the workgroups' dense partials.  A block owns 64 entries; 16
+// thread rows each add a contiguous segment of workgroups, and the segment
+// sums are added in order (the result does not depend on scheduling).
+static __global__ __launch_bounds__(kColBuckets * kColSegs) void bin_coarse_reduce_kernel(BinPlan plan, int n) {
+    __shared__ float seg[kColSegs][kColBuckets];
+    const int li = threadIdx.x % kColBuckets, sg = threadIdx.x / kColBuckets;
+    const int i = blockIdx.x * kColBuckets + li;
+    const int per = (plan.W + kColSegs - 1) / kColSegs;
+    const int w0 = sg * per, w1 = w0 + per < plan.W ? w0 + per : plan.W;
+    float s = 0.0f;
+    if (i < n)
+        for (int w = w0; w < w1; ++w) s += plan.partial[(size_t)w * n + i];
+    seg[sg][li] = s;
+    __syncthreads();
+    if (sg != 0 || i >= n) return;
+    float t = 0.0f;
+    for (int k = 0; k < kColSegs; ++k) t += seg[k][li];
+    plan.gdense[i] = t;
+}
+
 constexpr int kAccBlock = 512;
 constexpr int kAccUnroll = 4;
 
-template <int F, bool ADAM>
+// Adam update of four parameters with their summed gradients (the same
+// binary32 operation sequence as the standalone Adam kernel).
+__device__ __forceinline__ void adam4(const AdamArgs& a, f32x4 g, f32x4& p, f32x4& m, f32x4& v, f16x4& h) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        m[q] = a.b1 * m[q] + (1.0f - a.b1) * g[q];
+        v[q] = a.b2 * v[q] + (1.0f - a.b2) * g[q] * g[q];
+        p[q] = p[q] - a.lr * (m[q] * a.inv_bc1) / (sqrtf(v[q] * a.inv_bc2) + a.eps);
+        h[q] = (f16)p[q];
+    }
+}
+
+constexpr int kAccPre = 8;  // float4 chunks of the slice a thread preloads
+
+template <int D, int F, bool ADAM>
 __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint32_t T, float* __restrict__ d_tables,
                                                               AdamArgs adam) {
     extern __shared__ float acc[];
     const int S = 1 << plan.s_log2;
+    const int b = blockIdx.x;
+    const int l = plan.l0 + b / plan.bpl;
+    const size_t off = ((size_t)l * T + (size_t)(b % plan.bpl) * S) * F;
+    const int n4 = S * F / 4;
+    const float* base_ptr = ADAM ? adam.param : d_tables;
+    const bool vec = n4 * 4 == S * F && ((uintptr_t)(base_ptr + off) & 15) == 0 && n4 <= kAccPre * kAccBlock;
+    // The slice's state does not depend on the records: issue its loads first
+    // so they overlap the record phase.
+    f32x4 P[kAccPre], M[kAccPre], Vv[kAccPre];
+    if (vec) {
+#pragma unroll
+        for (int c = 0; c < kAccPre; ++c) {
+            const int i = threadIdx.x + c * kAccBlock;
+            if (i < n4) {
+                P[c] = reinterpret_cast<const f32x4*>(base_ptr + off)[i];
+                if constexpr (ADAM) {
+                    M[c] = reinterpret_cast<const f32x4*>(adam.m + off)[i];
+                    Vv[c] = reinterpret_cast<const f32x4*>(adam.v + off)[i];
+                }
+            }
+        }
+    }
     for (int i = threadIdx.x; i < S * F; i += kAccBlock) acc[i] = 0.0f;
     __syncthreads();
-    const int b = blockIdx.x;
+    // privatised level: pick up the dense sums whose slot falls in this bucket
+    if (l < plan.P) {
+        const int ext = plan.ext[l];
+        const uint32_t want = (uint32_t)(b % plan.bpl), smask = (uint32_t)S - 1u;
+        for (int e = plan.doff[l] + threadIdx.x; e < plan.doff[l + 1]; e += kAccBlock) {
+            int32_t rem = e - plan.doff[l];
+            uint32_t h = 0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                h ^= (uint32_t)(rem % ext) * hash_prime(i);
+                rem /= ext;
+            }
+            h &= T - 1u;
+            if ((h >> plan.s_log2) != want) continue;
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                const float g = plan.gdense[(size_t)e * F + j];
+                if (g != 0.0f) atomicAdd(&acc[(h & smask) * F + j], g);
+            }
+        }
+    }
     const BinRec<F>* __restrict__ recs = reinterpret_cast<const BinRec<F>*>(plan.recs);
     const uint32_t r0 = plan.base[b], r1 = plan.base[b + 1];
     uint32_t r = r0 + threadIdx.x;
@@ -194,32 +342,20 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
         for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], rec.v[j]);
     }
     __syncthreads();
-    const int l = plan.l0 + b / plan.bpl;
-    const size_t off = ((size_t)l * T + (size_t)(b % plan.bpl) * S) * F;
-    const int n4 = S * F / 4;  // S * F is a multiple of 4 whenever S >= 4
-    const float* base_ptr = ADAM ? adam.param : d_tables;
-    if (n4 * 4 == S * F && ((uintptr_t)(base_ptr + off) & 15) == 0) {
-        for (int i = threadIdx.x; i < n4; i += kAccBlock) {
+    if (vec) {
+#pragma unroll
+        for (int c = 0; c < kAccPre; ++c) {
+            const int i = threadIdx.x + c * kAccBlock;
+            if (i >= n4) break;
             const f32x4 g = reinterpret_cast<const f32x4*>(acc)[i];
             if constexpr (!ADAM) {
-                f32x4* out = reinterpret_cast<f32x4*>(d_tables + off) + i;
-                *out = *out + g;
+                reinterpret_cast<f32x4*>(d_tables + off)[i] = P[c] + g;
             } else {
-                f32x4* P = reinterpret_cast<f32x4*>(adam.param + off) + i;
-                f32x4* M = reinterpret_cast<f32x4*>(adam.m + off) + i;
-                f32x4* Vv = reinterpret_cast<f32x4*>(adam.v + off) + i;
-                f32x4 p = *P, m = *M, v = *Vv;
                 f16x4 h;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    m[q] = adam.b1 * m[q] + (1.0f - adam.b1) * g[q];
-                    v[q] = adam.b2 * v[q] + (1.0f - adam.b2) * g[q] * g[q];
-                    p[q] = p[q] - adam.lr * (m[q] * adam.inv_bc1) / (sqrtf(v[q] * adam.inv_bc2) + adam.eps);
-                    h[q] = (f16)p[q];
-                }
-                *P = p;
-                *M = m;
-                *Vv = v;
+                adam4(adam, g, P[c], M[c], Vv[c], h);
+                reinterpret_cast<f32x4*>(adam.param + off)[i] = P[c];
+                reinterpret_cast<f32x4*>(adam.m + off)[i] = M[c];
+                reinterpret_cast<f32x4*>(adam.v + off)[i] = Vv[c];
                 if (adam.param_f16) reinterpret_cast<f16x4*>((f16*)adam.param_f16 + off)[i] = h;
             }
         }
@@ -229,6 +365,7 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
             if constexpr (!ADAM) {
                 d_tables[off + i] += g;
             } else {
+#pragma clang fp contract(off)
                 const float m = adam.b1 * adam.m[off + i] + (1.0f - adam.b1) * g;
                 const float v = adam.b2 * adam.v[off + i] + (1.0f - adam.b2) * g * g;
                 const float p = adam.param[off + i] - adam.lr * (m * adam.inv_bc1) / (sqrtf(v * adam.inv_bc2) + adam.eps);
@@ -245,20 +382,27 @@ template <class Tag, int D, int F, typename GT>
 hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
     const GT* d_out = (const GT*)c.d_out;
     bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
+    if (p.P > 0) {
+        const int n = p.Dtot * F;
+        bin_coarse_kernel<Tag, D, F, GT><<<p.W, kBinBlock, (size_t)n * sizeof(float), c.stream>>>(c.N, c.pts, d_out,
+                                                                                                c.lv, p);
+        bin_coarse_reduce_kernel<<<(n + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, n);
+    }
     bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
     bin_scan_kernel<<<1, 1024, 0, c.stream>>>(p.B, totals, p.base);
     bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv, p);
     const size_t lds = (size_t)(F << p.s_log2) * sizeof(float);
     if (c.adam.param)
-        bin_accum_kernel<F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, nullptr, c.adam);
+        bin_accum_kernel<D, F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, nullptr, c.adam);
     else
-        bin_accum_kernel<F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, c.d_tables, c.adam);
+        bin_accum_kernel<D, F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, c.d_tables, c.adam);
     return hipGetLastError();
 }
 
 template <class Tag, int D, int F>
 hipError_t binned_adjoint(const EncodeCall& c) {
-    BinLayout lay = bin_layout(c.D, c.F, c.lv.L, 31 - __builtin_clz(c.lv.mask + 1u), c.N, Tag::simplex);
+    BinLayout lay = bin_layout(c.D, c.F, c.lv.L, 31 - __builtin_clz(c.lv.mask + 1u), c.N, Tag::simplex, c.lv.sigma,
+                               (double)c.lv.reach);
     char* ws = (char*)c.workspace;
     for (int g = 0; g < lay.groups; ++g) {
         BinPlan p = bin_plan(lay, g, ws);

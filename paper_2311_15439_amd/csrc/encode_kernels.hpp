@@ -90,29 +90,40 @@ struct RowIO<f16, F> {
 
 // ---- visiting the vertices of one level ---------------------------------
 // fn(h, w, base) is called with arrays of K slots and weights; base is the
-// index of the first of them in the level's vertex list.
+// index of the first of them in the level's vertex list.  visit_level_ex
+// also passes the cell corner and, per vertex, the axes on which it is one
+// step above the corner.
 
 template <int D, class Fn>
-__device__ __forceinline__ void visit_level(SimplexTag, const float (&y)[D], float sigma, uint32_t mask,
-                                            Fn&& fn) {
-    uint32_t h[D + 1];
+__device__ __forceinline__ void visit_level_ex(SimplexTag, const float (&y)[D], float sigma, uint32_t mask,
+                                               Fn&& fn) {
+    uint32_t h[D + 1], offs[D + 1];
     float w[D + 1];
-    SimplexCell<D>::lookup(y, sigma, mask, h, w);
-    fn(h, w, 0);
+    int32_t cell[D];
+    SimplexCell<D>::lookup(y, sigma, mask, h, w, cell, offs);
+    fn(h, w, 0, cell, offs);
 }
 
 template <int D, class Fn>
-__device__ __forceinline__ void visit_level(GridTag, const float (&x)[D], float sigma, uint32_t mask,
-                                            Fn&& fn) {
+__device__ __forceinline__ void visit_level_ex(GridTag, const float (&x)[D], float sigma, uint32_t mask,
+                                               Fn&& fn) {
     typename GridCell<D>::Low lo;
     GridCell<D>::lookup_low(x, sigma, lo);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-        uint32_t h[GridCell<D>::VH];
+        uint32_t h[GridCell<D>::VH], offs[GridCell<D>::VH];
         float w[GridCell<D>::VH];
         GridCell<D>::corners(lo, half, mask, h, w);
-        fn(h, w, half * GridCell<D>::VH);
+#pragma unroll
+        for (int c = 0; c < GridCell<D>::VH; ++c) offs[c] = (uint32_t)(c + half * GridCell<D>::VH);
+        fn(h, w, half * GridCell<D>::VH, lo.cell, offs);
     }
+}
+
+template <class Tag, int D, class Fn>
+__device__ __forceinline__ void visit_level(Tag tag, const float (&y)[D], float sigma, uint32_t mask, Fn&& fn) {
+    visit_level_ex(tag, y, sigma, mask,
+                   [&](const auto& h, const auto& w, int base, const auto&, const auto&) { fn(h, w, base); });
 }
 
 template <class Tag, int D>

@@ -48,9 +48,12 @@ struct SimplexCell {
     static constexpr int VH = D + 1;  // vertices handled per half (one half)
     static constexpr int HALVES = 1;
 
-    // h[k], w[k] for k = 0..D: the walk's vertices.
+    // h[k], w[k] for k = 0..D: the walk's vertices.  cell receives the cell
+    // corner and offs[k] the set of axes (bit i = axis i) on which vertex k
+    // is one step above it; callers that ignore them pay nothing (inlined).
     __device__ __forceinline__ static void lookup(const float (&y)[D], float sigma, uint32_t mask,
-                                                  uint32_t (&h)[V], float (&w)[V]) {
+                                                  uint32_t (&h)[V], float (&w)[V], int32_t (&cell)[D],
+                                                  uint32_t (&offs)[V]) {
 #pragma clang fp contract(off)
         float f[D];
         uint32_t a[D];
@@ -59,7 +62,8 @@ struct SimplexCell {
             const float p = y[i] * sigma;
             const float fl = floorf(p);
             f[i] = p - fl;
-            a[i] = (uint32_t)(int32_t)fl * hash_prime(i);
+            cell[i] = (int32_t)fl;
+            a[i] = (uint32_t)cell[i] * hash_prime(i);
         }
         int r[D];
 #pragma unroll
@@ -86,10 +90,14 @@ struct SimplexCell {
         w[D] = fs[D - 1];
 #pragma unroll
         for (int k = 0; k <= D; ++k) {
-            uint32_t hk = 0;
+            uint32_t hk = 0, ok = 0;
 #pragma unroll
-            for (int i = 0; i < D; ++i) hk ^= (r[i] < k) ? a[i] + hash_prime(i) : a[i];
+            for (int i = 0; i < D; ++i) {
+                hk ^= (r[i] < k) ? a[i] + hash_prime(i) : a[i];
+                ok |= (r[i] < k) ? (1u << i) : 0u;
+            }
             h[k] = hk & mask;
+            offs[k] = ok;
         }
     }
 };
@@ -111,6 +119,7 @@ struct GridCell {
         float w[VH];
         float ft, gt;       // top-axis factors f, 1 - f
         uint32_t at, bt;    // top-axis hash terms for bit 0 / bit 1
+        int32_t cell[D];    // cell corner
     };
 
     __device__ __forceinline__ static void lookup_low(const float (&x)[D], float sigma, Low& lo) {
@@ -123,7 +132,8 @@ struct GridCell {
             const float fl = floorf(p);
             f[i] = p - fl;
             g[i] = 1.0f - f[i];
-            a[i] = (uint32_t)(int32_t)fl * hash_prime(i);
+            lo.cell[i] = (int32_t)fl;
+            a[i] = (uint32_t)lo.cell[i] * hash_prime(i);
             b[i] = a[i] + hash_prime(i);
         }
         lo.w[0] = 1.0f;

@@ -13,6 +13,7 @@ struct GridTag { static constexpr bool simplex = false; };
 // Per-call level parameters, passed to the kernels by value.
 struct LevelArgs {
     float sigma[32];  // binary32 multiplier of level l
+    float reach;      // largest pre-scale coordinate of the unit cube (sqrt(n+1) or 1)
     float Fn;         // skew factor F_n in binary32
     uint32_t mask;    // T - 1
     int32_t L;        // number of levels
@@ -31,31 +32,45 @@ struct AdamArgs {
 enum class EncodeOp { Forward, Adjoint, AdjointBinned, Debug };
 
 // Binned adjoint: one level group's plan (device pointers into the caller's
-// workspace).
+// workspace).  Levels [0, P) of group 0 are privatised: their contributions
+// from cells inside a dense box of ext[l]^n vertices are summed per
+// workgroup in LDS instead of being emitted as records.
 struct BinPlan {
     int l0, l1;       // levels [l0, l1) of this group
     int s_log2;       // slots per bucket = 2^s_log2
     int bpl;          // buckets per level
     int B;            // buckets in this group
-    int W;            // workgroups of the count and scatter passes
+    int W;            // workgroups of the count, coarse and scatter passes
     int64_t chunk;    // points per workgroup
+    int P;            // privatised levels (all below l1)
+    int Dtot;         // dense entries over the privatised levels
+    int ext[32];      // dense box extent per privatised level
+    int doff[33];     // first dense entry of each privatised level
     uint32_t* counts;  // [W][B]
     uint32_t* base;    // [B + 1]
     void* recs;        // records
+    float* partial;    // [W][Dtot * F] per-workgroup dense sums
+    float* gdense;     // [Dtot * F] their total
 };
 
-// Sizes shared by every group; a pure function of the encoding and N so the
-// workspace query and the launch agree.
+// Sizes shared by every group; a pure function of the encoding, its level
+// multipliers and N, so the workspace query and the launch agree.
 struct BinLayout {
-    int L, lpg, groups, s_log2, bpl, Bmax, W, rec_bytes, V;
+    int L, lpg, groups, s_log2, bpl, Bmax, W, rec_bytes, V, P, Dtot;
+    int ext[32];
+    int doff[33];
     int64_t N, chunk;
-    size_t off_counts, off_base, off_totals, off_recs, total_bytes;
+    size_t off_counts, off_base, off_totals, off_recs, off_partial, off_gdense, total_bytes;
     bool ok;
 };
 
 inline size_t bin_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
-inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simplex) {
+// sigma: binary32 level multipliers; reach: largest skewed coordinate of a
+// point of the unit cube before scaling (sqrt(n+1) for the simplex, 1 for
+// the grid).
+inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simplex, const float* sigma,
+                            double reach) {
     BinLayout b{};
     b.L = L;
     b.N = N;
@@ -84,6 +99,22 @@ inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simp
     int64_t W = (N + 255) / 256;
     b.W = (int)(W < 512 ? (W > 0 ? W : 1) : 512);
     b.chunk = (N + b.W - 1) / b.W;
+    // privatised coarse levels: the prefix of group 0 whose dense boxes fit
+    // in 96 KiB of binary32 accumulators
+    const int dense_max = (96 * 1024) / (4 * F);
+    b.P = 0;
+    b.Dtot = 0;
+    b.doff[0] = 0;
+    for (int l = 0; l < lpg && l < 32; ++l) {
+        const double e = floor((double)sigma[l] * reach) + 2.0;
+        double size = 1.0;
+        for (int i = 0; i < D; ++i) size *= e;
+        if (size > (double)(dense_max - b.Dtot)) break;
+        b.ext[l] = (int)e;
+        b.Dtot += (int)size;
+        b.P = l + 1;
+        b.doff[l + 1] = b.Dtot;
+    }
     size_t off = 0;
     b.off_counts = off;
     off = bin_align(off + (size_t)b.W * b.Bmax * 4);
@@ -91,6 +122,10 @@ inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simp
     off = bin_align(off + ((size_t)b.Bmax + 1) * 4);
     b.off_totals = off;
     off = bin_align(off + (size_t)b.Bmax * 4);
+    b.off_partial = off;
+    off = bin_align(off + (size_t)b.W * b.Dtot * F * 4);
+    b.off_gdense = off;
+    off = bin_align(off + (size_t)b.Dtot * F * 4);
     b.off_recs = off;
     off = bin_align(off + (size_t)N * lpg * b.V * b.rec_bytes);
     b.total_bytes = off;
@@ -106,9 +141,15 @@ inline BinPlan bin_plan(const BinLayout& lay, int g, char* ws) {
     p.B = (p.l1 - p.l0) * lay.bpl;
     p.W = lay.W;
     p.chunk = lay.chunk;
+    p.P = g == 0 ? lay.P : 0;
+    p.Dtot = g == 0 ? lay.Dtot : 0;
+    for (int l = 0; l < 32; ++l) p.ext[l] = lay.ext[l];
+    for (int l = 0; l < 33; ++l) p.doff[l] = lay.doff[l];
     p.counts = (uint32_t*)(ws + lay.off_counts);
     p.base = (uint32_t*)(ws + lay.off_base);
     p.recs = ws + lay.off_recs;
+    p.partial = (float*)(ws + lay.off_partial);
+    p.gdense = (float*)(ws + lay.off_gdense);
     return p;
 }
 

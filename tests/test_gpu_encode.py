@@ -188,7 +188,10 @@ def test_bwd_parity(case, binned):
     n, res, log2_T, F, dout_f16, cell = case
     g, o = _enc_pair(n, res, log2_T, F, False, cell)
     N = (1 << 17) + 3 if n == 6 and cell == spx.SPX_GRID else 6001
-    pts = inputs.uniform_points(N, n, 500 + n)
+    # uniform points plus edge points, some outside the unit cube (their
+    # coarse cells fall outside the binned path's dense boxes)
+    pts = np.concatenate([inputs.uniform_points(N, n, 500 + n),
+                          _special_points(n, np.random.default_rng(n)), -0.5 + 2.0 * inputs.uniform_points(97, n, 9)])
     d = inputs.gradients(len(pts), len(res) * F, 600 + n)
     if dout_f16:
         d = d.astype(np.float16)
