@@ -153,6 +153,8 @@ __global__ __launch_bounds__(kBlock) void encode_fwd_kernel(int64_t N, const flo
         float y[D];
         load_point<Tag, D>(pts, pt, lv.Fn, y);
         OT* __restrict__ orow = out + pt * (int64_t)(lv.L * F);
+        // unrolled so that several levels' gathers are in flight together
+#pragma unroll 4
         for (int l = 0; l < lv.L; ++l) {
             const TT* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * F);
             float acc[F];

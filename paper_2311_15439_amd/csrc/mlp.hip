@@ -120,17 +120,11 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(int64_t N, const _Float16*
 
 // ----------------------------------------------------------------- backward
 
-typedef short s4 __attribute__((ext_vector_type(4)));
-
-// 16x16x16 bfloat16 MFMA for the weight gradients (k = 16 points).
-__device__ __forceinline__ f4 mma_b16(s4 a, s4 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
 __device__ __forceinline__ short bf_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
 
 constexpr int kBwdWaves = 4;
 constexpr int kPts = 16;  // points per wave per iteration
-constexpr int kMaxBwdGroups = 256;
+constexpr int kMaxBwdGroups = 512;
 
 template <int DIN>
 struct BwdLayout {
@@ -143,12 +137,15 @@ struct BwdLayout {
     static constexpr int NFRAG = F_W1T + 2 * (DIN / 16);
     static constexpr int FRAG_BYTES = NFRAG * 64 * 16;
     // per-wave transpose area: one row of 16 points (bf16) per unit
-    static constexpr int R_DY = 0, R_H2 = 16, R_H1 = 80, R_DA2 = 144, R_DA1 = 208;
-    static constexpr int ROWS = 272;
+    static constexpr int R_DY = 0, R_H2 = 16, R_H1 = 80, R_DA2 = 144, R_DA1 = 208, R_X = 272;
+    static constexpr int ROWS = R_X + DIN;
     static constexpr int WAVE_BYTES = ROWS * kPts * 2;
     static constexpr int PARTIAL = H * DIN + H * H + 16 * H;  // floats per workgroup
-    static constexpr int AREA = kBwdWaves * WAVE_BYTES > PARTIAL * 4 ? kBwdWaves * WAVE_BYTES : PARTIAL * 4;
-    static constexpr int LDS_BYTES = FRAG_BYTES + AREA;
+    static constexpr int LDS_BYTES = FRAG_BYTES + kBwdWaves * WAVE_BYTES;
+    // weight-gradient tiles (16x16 each): dW3 4, dW2 16, dW1 4 * DIN/16;
+    // wave w owns tiles w, w + 4, w + 8, ...
+    static constexpr int TILES = 4 + 16 + 4 * (DIN / 16);
+    static constexpr int TPW = TILES / kBwdWaves;
 };
 
 template <int DIN>
@@ -207,19 +204,13 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
     auto fh = [&](int f) { uint4 u = frag[f * 64 + lane]; return *reinterpret_cast<h8*>(&u); };
     auto fb = [&](int f) { uint4 u = frag[f * 64 + lane]; return *reinterpret_cast<b8*>(&u); };
 
-    short* S = reinterpret_cast<short*>(lds + Lay::FRAG_BYTES + wv * Lay::WAVE_BYTES);
-    // operand with 4 consecutive points (4q..4q+3) of one unit row
-    auto sread = [&](int row) { return *reinterpret_cast<const s4*>(S + row * kPts + 4 * q); };
+    short* const S0 = reinterpret_cast<short*>(lds + Lay::FRAG_BYTES);
+    short* S = S0 + wv * (Lay::WAVE_BYTES / 2);
+    static_assert(Lay::TILES % kBwdWaves == 0, "tiles must split evenly over the waves");
 
-    f4 acc1[4][TIN], acc2[4][4], acc3[4];
+    f4 acc[Lay::TPW];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        acc3[t] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < TIN; ++s) acc1[t][s] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) acc2[t][s] = f4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int u = 0; u < Lay::TPW; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int64_t per_iter = (int64_t)kBwdWaves * kPts;
     const int64_t iters = (N + per_iter - 1) / per_iter;
@@ -299,60 +290,60 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
                 S[(Lay::R_DA2 + u) * kPts + r] = bf_bits(da2[t][i]);
                 S[(Lay::R_DA1 + u) * kPts + r] = bf_bits(da1[t][i]);
             }
-        // dW1's point-major input operand straight from memory (4 points per lane)
-        s4 xk[TIN];
 #pragma unroll
-        for (int s = 0; s < TIN; ++s)
+        for (int s = 0; s < KS1; ++s)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t pp = base + 4 * q + i;
-                xk[s][i] = bf_bits(pp < N ? (float)x[pp * DIN + 16 * s + r] : 0.0f);
-            }
+            for (int j = 0; j < 8; ++j) S[(Lay::R_X + 32 * s + k_load(q, j)) * kPts + r] = bf_bits((float)xb[s][j]);
         __syncthreads();
+        // Weight gradients over the iteration's 64 points: this wave's tiles,
+        // k = 32 points per MFMA (lane group q reads 8 points of region
+        // 2c + q / 2; A and B use the same assignment).
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc3[t] = mma_b16(sread(Lay::R_DY + r), sread(Lay::R_H2 + 16 * t + r), acc3[t]);
+        for (int u = 0; u < Lay::TPW; ++u) {
+            const int tile = wv + kBwdWaves * u;
+            int ra, rb;
+            if (tile < 4) {
+                ra = Lay::R_DY + r;
+                rb = Lay::R_H2 + 16 * tile + r;
+            } else if (tile < 20) {
+                ra = Lay::R_DA2 + 16 * ((tile - 4) / 4) + r;
+                rb = Lay::R_H1 + 16 * ((tile - 4) % 4) + r;
+            } else {
+                ra = Lay::R_DA1 + 16 * ((tile - 20) / TIN) + r;
+                rb = Lay::R_X + 16 * ((tile - 20) % TIN) + r;
+            }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const s4 a = sread(Lay::R_DA2 + 16 * t + r);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc2[t][s] = mma_b16(a, sread(Lay::R_H1 + 16 * s + r), acc2[t][s]);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const s4 a = sread(Lay::R_DA1 + 16 * t + r);
-#pragma unroll
-            for (int s = 0; s < TIN; ++s) acc1[t][s] = mma_b16(a, xk[s], acc1[t][s]);
+            for (int c = 0; c < kBwdWaves / 2; ++c) {
+                const short* reg = S0 + (2 * c + (q >> 1)) * (Lay::WAVE_BYTES / 2);
+                const b8 a = *reinterpret_cast<const b8*>(reg + ra * kPts + 8 * (q & 1));
+                const b8 bb = *reinterpret_cast<const b8*>(reg + rb * kPts + 8 * (q & 1));
+                acc[u] = mma_b(a, bb, acc[u]);
+            }
         }
         __syncthreads();
     }
 
-    // ---- reduce the four waves in a fixed order, then write this group's partial
-    float* P = reinterpret_cast<float*>(lds + Lay::FRAG_BYTES);
-    for (int w = 0; w < kBwdWaves; ++w) {
-        if (wv == w) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int row = 16 * t + 4 * q + i;
-#pragma unroll
-                    for (int s = 0; s < TIN; ++s) {
-                        float& d = P[row * DIN + 16 * s + r];
-                        d = (w == 0 ? 0.0f : d) + acc1[t][s][i];
-                    }
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        float& d = P[H * DIN + row * H + 16 * s + r];
-                        d = (w == 0 ? 0.0f : d) + acc2[t][s][i];
-                    }
-                    float& d3 = P[H * DIN + H * H + (4 * q + i) * H + 16 * t + r];
-                    d3 = (w == 0 ? 0.0f : d3) + acc3[t][i];
-                }
-        }
-        __syncthreads();
-    }
+    // ---- each wave writes its own tiles of this group's partial
     float* out = partial + (size_t)blockIdx.x * Lay::PARTIAL;
-    for (int i = tid; i < Lay::PARTIAL; i += 256) out[i] = P[i];
+#pragma unroll
+    for (int u = 0; u < Lay::TPW; ++u) {
+        const int tile = wv + kBwdWaves * u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 4 * q + i;  // D layout: lane holds column r, rows 4q..4q+3
+            size_t idx;
+            if (tile < 4) {
+                idx = (size_t)H * DIN + H * H + row * H + 16 * tile + r;  // dW3[out][hidden]
+            } else if (tile < 20) {
+                const int t = (tile - 4) / 4, s = (tile - 4) % 4;
+                idx = (size_t)H * DIN + (16 * t + row) * H + 16 * s + r;  // dW2[out][in]
+            } else {
+                const int t = (tile - 20) / TIN, s = (tile - 20) % TIN;
+                idx = (size_t)(16 * t + row) * DIN + 16 * s + r;  // dW1[hidden][in]
+            }
+            out[idx] = acc[u][i];
+        }
+    }
 }
 
 // Sum the per-group partials and scatter into dW1/dW2/dW3.  A block owns 64
