@@ -1,0 +1,103 @@
+"""GPU: the autograd wrappers give the oracle's values and gradients, the
+fused field equals the composition of its parts, and a small field trains."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_15439_amd import inputs, spx
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _oracle_enc(m):
+    e = m.enc
+    return oracle.Encoding(e.n_dims, list(e.res), e.log2_T, e.n_feat, table_dtype=oracle.F16, cell=e.cell)
+
+
+def test_encoding_fn_matches_oracle():
+    from paper_2311_15439_amd.torch_ops import SimplexEncoding
+    m = SimplexEncoding(3, n_levels=4, log2_T=14, n_min=8, n_max=200, init_scale=1.0, seed=1)
+    pts = inputs.uniform_points(5000, 3, 2)
+    tp = torch.from_numpy(pts).to(DEV)
+    out = m(tp)
+    G = inputs.gradients(5000, 8, 3)
+    (out * torch.from_numpy(G).to(DEV)).sum().backward()
+    torch.cuda.synchronize()
+    oe = _oracle_enc(m)
+    tab16 = m.table_f16.cpu().numpy()
+    np.testing.assert_array_equal(tab16, m.params.detach().cpu().numpy().astype(np.float16))
+    ref = oracle.encode_fwd(oe, pts, tab16)
+    mag = oracle.encode_fwd_absmag(oe, pts, tab16)
+    assert (np.abs(out.detach().cpu().numpy() - ref) <= 1e-5 * mag + 1e-30).all()
+    gref, gmag, cnt = oracle.encode_bwd(oe, pts, G.astype(np.float64), with_stats=True)
+    assert (np.abs(m.params.grad.cpu().numpy() - gref) <= (cnt + 5) * 2.0 ** -24 * gmag + 1e-30).all()
+
+
+def test_mlp_fn_matches_oracle():
+    from paper_2311_15439_amd.torch_ops import TinyMLP
+    net = TinyMLP(32, 3, seed=4)
+    x = inputs.features_f16(3000, 32, 5).astype(np.float32)
+    tx = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    y = net(tx)
+    gy = inputs.gradients(3000, 3, 6)
+    (y * torch.from_numpy(gy).to(DEV)).sum().backward()
+    torch.cuda.synchronize()
+    W16 = [w.detach().cpu().numpy().astype(np.float16) for w in (net.W1, net.W2, net.W3)]
+    ref, mag = oracle.mlp_fwd(x.astype(np.float16), *W16, with_absmag=True)
+    assert (np.abs(y.detach().cpu().numpy() - ref) <= 2.0 ** -9 * mag + 1e-6).all()
+    r = oracle.mlp_bwd(x.astype(np.float16), *W16, gy)
+    keep = r["margin"] >= 1e-3
+    scale = np.abs(r["d_x"][keep]).max()
+    assert np.abs(tx.grad.cpu().numpy()[keep] - r["d_x"][keep]).max() <= 2.0 ** -5 * scale
+    for k, w in [("dW1", net.W1), ("dW2", net.W2), ("dW3", net.W3)]:
+        assert np.abs(w.grad.cpu().numpy() - r[k]).max() <= 2.0 ** -5 * np.abs(r[k]).max(), k
+
+
+def test_field_equals_composition():
+    from paper_2311_15439_amd.torch_ops import NeuralField, SimplexEncoding, TinyMLP
+    enc = SimplexEncoding(2, n_levels=16, log2_T=16, n_min=16, n_max=2048, init_scale=0.5, seed=7)
+    net = TinyMLP(32, 3, seed=8)
+    field = NeuralField(enc, net)
+    pts = torch.from_numpy(inputs.pixel_points(20000, 9, width=4096)).to(DEV)
+    gy = torch.from_numpy(inputs.gradients(20000, 3, 10)).to(DEV)
+    y1 = field(pts)
+    (y1 * gy).sum().backward()
+    g1 = [p.grad.clone() for p in (enc.params, net.W1, net.W2, net.W3)]
+    for p in (enc.params, net.W1, net.W2, net.W3):
+        p.grad = None
+    y2 = net(enc(pts))
+    (y2 * gy).sum().backward()
+    g2 = [p.grad.clone() for p in (enc.params, net.W1, net.W2, net.W3)]
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)  # same binary16 features, same kernels
+    for a, b in zip(g1[1:], g2[1:]):
+        assert torch.equal(a, b)  # weight gradients are reduced in a fixed order
+    # table gradients: same contributions, summation order may differ
+    scale = (g1[0].abs() + g2[0].abs()).max()
+    assert ((g1[0] - g2[0]).abs() <= 1e-5 * scale).all()
+
+
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+def test_small_field_trains(cell):
+    """200 Adam steps on a synthetic RGB target lower the loss several-fold
+    for the simplex and the grid encodings alike."""
+    from paper_2311_15439_amd.torch_ops import NeuralField, SimplexEncoding, TinyMLP
+    torch.manual_seed(0)
+    enc = SimplexEncoding(2, n_levels=16, log2_T=16, n_min=16, n_max=1024, cell=cell,
+                          equal_memory=(cell == spx.SPX_SIMPLEX), seed=1)
+    net = TinyMLP(32, 3, seed=2)
+    field = NeuralField(enc, net)
+    opt = torch.optim.Adam(field.parameters(), lr=1e-2, betas=(0.9, 0.99), eps=1e-15)
+    losses = []
+    for step in range(200):
+        pts = inputs.pixel_points(1 << 14, 100 + step, width=1024)
+        tgt = torch.from_numpy(inputs.procedural_rgb(pts, 4)).to(DEV)
+        y = field(torch.from_numpy(pts).to(DEV))
+        loss = torch.mean((y - tgt) ** 2)
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:5]), (losses[:5], losses[-20:])
