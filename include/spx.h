@@ -266,6 +266,67 @@ spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const u
                        float* dW2, float* dW3, void* workspace, size_t workspace_bytes,
                        hipStream_t stream);
 
+/*
+ * Serving: several resident fields (encoding + network), queried together.
+ *
+ * spx_field is a device-ready descriptor of one field, filled on the host by
+ * spx_field_init() (which also computes the level multipliers) and copied by
+ * the caller into a device array.  Supported fields: n_dims 2 or 3, 16
+ * levels of 2 binary16 features (32 network inputs), hidden width 64,
+ * d_out 1..16, simplex or grid cells.
+ */
+typedef struct {
+    float sigma[SPX_MAX_LEVELS]; /* binary32 level multipliers */
+    float Fn;                    /* skew factor F_n (binary32) */
+    uint32_t mask;               /* T - 1 */
+    int32_t n_dims;
+    int32_t n_levels;
+    int32_t cell;
+    int32_t d_out;
+    const void* tables;          /* device [16][T][2] binary16, 4-byte aligned */
+    const uint16_t* W1;          /* device [64][32] binary16, 16-byte aligned */
+    const uint16_t* W2;          /* device [64][64] binary16 */
+    const uint16_t* W3;          /* device [d_out][64] binary16 */
+} spx_field;
+
+/*
+ * One segment of a batched query: count points of one field.
+ *   pts         device [count][n_dims] binary32, 4-byte aligned
+ *   out         device [count][d_out] binary32, overwritten
+ *   first_tile  sum of ceil(count / 16) over all earlier segments of the
+ *               batch (segments are processed in 16-point tiles)
+ *   field       index into the fields array; a segment with an index
+ *               outside [0, nfields) is skipped (its out is not written)
+ */
+typedef struct {
+    const float* pts;
+    float* out;
+    int64_t count;
+    int64_t first_tile;
+    int32_t field;
+    int32_t pad;
+} spx_segment;
+
+/*
+ * Host helper: validate a field and fill *out (host memory).  enc must be a
+ * 2- or 3-D encoding with 16 levels, 2 features and binary16 tables.
+ */
+spx_status spx_field_init(const spx_encoding* enc, const void* tables, const uint16_t* W1, const uint16_t* W2,
+                          const uint16_t* W3, int32_t d_out, spx_field* out);
+
+/*
+ * Encoding forward and network forward for every point of every segment, in
+ * one launch (Sec. 5 steps (a)-(e) at inference).  fields: device
+ * [nfields]; segs: device [nseg] with consistent first_tile values and
+ * total_tiles = sum of ceil(count / 16).  Results are bit-identical to
+ * spx_encode_fwd (binary16 features) followed by spx_mlp_fwd, whatever the
+ * batch composition.  Inconsistent first_tile values cannot make the kernel
+ * access memory outside a segment's pts/out ranges, but some points may then
+ * not be computed.
+ */
+spx_status spx_field_query_batched(const spx_field* fields, int32_t nfields, const spx_segment* segs, int32_t nseg,
+                                   int64_t total_tiles, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libspx.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPX_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "encode_simplex.hip", "encode_grid.hip", "mlp.hip", "optim.hip"]
+SOURCES = ["api.hip", "encode_simplex.hip", "encode_grid.hip", "mlp.hip", "optim.hip", "field_query.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -34,6 +34,7 @@ PER_FILE = {
     # the fused adjoint + Adam (in the encode units) and the standalone Adam
     # perform the same binary32 operation sequence
     "optim.hip": ["-ffp-contract=off"],
+    "field_query.hip": ["-ffp-contract=off"],
 }
 
 

@@ -304,6 +304,43 @@ spx_status spx_mse_grad(int64_t n, const float* y, const float* target, float* d
     return from_hip(spx::mse_grad(n, y, target, d_y, scale, stream), "spx_mse_grad launch");
 }
 
+spx_status spx_field_init(const spx_encoding* enc, const void* tables, const uint16_t* W1, const uint16_t* W2,
+                          const uint16_t* W3, int32_t d_out, spx_field* out) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if (!out) return fail(SPX_EINVAL, "out is NULL");
+    if (enc->n_dims != 2 && enc->n_dims != 3) return fail(SPX_EUNSUPPORTED, "fields are 2- or 3-D (n_dims=%d)", enc->n_dims);
+    if (enc->n_levels != 16 || enc->n_feat != 2 || enc->table_dtype != SPX_F16)
+        return fail(SPX_EUNSUPPORTED, "fields use 16 levels of 2 binary16 features");
+    if (d_out < 1 || d_out > 16) return fail(SPX_EINVAL, "d_out=%d outside 1..16", d_out);
+    if (!tables || !W1 || !W2 || !W3) return fail(SPX_EINVAL, "NULL table or weight pointer");
+    if (!aligned(tables, 4) || !aligned(W1, 16) || !aligned(W2, 16) || !aligned(W3, 16))
+        return fail(SPX_EALIGN, "tables must be 4-byte and weights 16-byte aligned");
+    memset(out, 0, sizeof(*out));
+    const spx::LevelArgs lv = level_args(enc);
+    for (int l = 0; l < enc->n_levels; ++l) out->sigma[l] = lv.sigma[l];
+    out->Fn = lv.Fn;
+    out->mask = lv.mask;
+    out->n_dims = enc->n_dims;
+    out->n_levels = enc->n_levels;
+    out->cell = enc->cell;
+    out->d_out = d_out;
+    out->tables = tables;
+    out->W1 = W1;
+    out->W2 = W2;
+    out->W3 = W3;
+    return SPX_OK;
+}
+
+spx_status spx_field_query_batched(const spx_field* fields, int32_t nfields, const spx_segment* segs, int32_t nseg,
+                                   int64_t total_tiles, hipStream_t stream) {
+    if (nfields < 0 || nseg < 0 || total_tiles < 0) return fail(SPX_EINVAL, "negative count");
+    if (nseg == 0 || total_tiles == 0) return SPX_OK;
+    if (!fields || !segs) return fail(SPX_EINVAL, "fields or segs is NULL");
+    if (!aligned(fields, 8) || !aligned(segs, 8)) return fail(SPX_EALIGN, "fields/segs not 8-byte aligned");
+    return from_hip(spx::field_query(fields, nfields, segs, nseg, total_tiles, stream), "spx_field_query_batched launch");
+}
+
 static spx_status check_mlp(const spx_mlp* mlp, int64_t N) {
     if (!mlp) return fail(SPX_EINVAL, "mlp descriptor is NULL");
     if (N < 0) return fail(SPX_EINVAL, "N < 0");

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "spx.h"
+
 namespace spx {
 
 struct SimplexTag { static constexpr bool simplex = true; };
@@ -192,6 +194,8 @@ int mlp_bwd_lds_bytes(int d_in);
 hipError_t mlp_fwd(const MlpCall& c);
 hipError_t mlp_bwd(const MlpCall& c);
 
+hipError_t field_query(const spx_field* fields, int nfields, const spx_segment* segs, int nseg, int64_t total_tiles,
+                       hipStream_t s);
 hipError_t mse_grad(int64_t n, const float* y, const float* target, float* d_y, float scale, hipStream_t s);
 hipError_t cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t s);
 hipError_t adam_step(int64_t n, float* param, float* grad, float* m, float* v, uint16_t* param_f16, float lr,

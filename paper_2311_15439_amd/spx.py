@@ -36,6 +36,17 @@ class spx_encoding(C.Structure):
                 ("equal_memory", C.c_int32), ("res", C.c_int32 * MAX_LEVELS)]
 
 
+class spx_field(C.Structure):
+    _fields_ = [("sigma", C.c_float * MAX_LEVELS), ("Fn", C.c_float), ("mask", C.c_uint32),
+                ("n_dims", C.c_int32), ("n_levels", C.c_int32), ("cell", C.c_int32), ("d_out", C.c_int32),
+                ("tables", C.c_void_p), ("W1", C.c_void_p), ("W2", C.c_void_p), ("W3", C.c_void_p)]
+
+
+class spx_segment(C.Structure):
+    _fields_ = [("pts", C.c_void_p), ("out", C.c_void_p), ("count", C.c_int64), ("first_tile", C.c_int64),
+                ("field", C.c_int32), ("pad", C.c_int32)]
+
+
 class spx_mlp(C.Structure):
     _fields_ = [("d_in", C.c_int32), ("hidden", C.c_int32), ("d_out", C.c_int32)]
 
@@ -57,6 +68,8 @@ _SIGNATURES = {
     "spx_cast_f32_f16": (C.c_int, [C.c_int64, _P, _P, _P]),
     "spx_adam_step": (C.c_int, [C.c_int64, _P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
                                 C.c_float, C.c_int64, C.c_int32, _P]),
+    "spx_field_init": (C.c_int, [_P, _P, _P, _P, _P, C.c_int32, _P]),
+    "spx_field_query_batched": (C.c_int, [_P, C.c_int32, _P, C.c_int32, C.c_int64, _P]),
     "spx_mse_grad": (C.c_int, [C.c_int64, _P, _P, _P, C.c_float, _P]),
     "spx_mlp_fwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P]),
     "spx_mlp_bwd_workspace": (C.c_int, [_P, C.c_int64, _P]),
@@ -341,3 +354,27 @@ def spx_mlp_bwd(mlp: spx_mlp, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, workspace,
                              _dev(dW1, f, "dW1"), _dev(dW2, f, "dW2"), _dev(dW3, f, "dW3"),
                              _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)),
            "spx_mlp_bwd")
+
+
+# --------------------------------------------------------------- serving
+
+def spx_field_init(enc: Encoding, tables, W1, W2, W3, d_out: int) -> spx_field:
+    """Host descriptor of a resident field (tables and weights stay on the GPU)."""
+    torch = _torch()
+    out = spx_field()
+    h = torch.float16
+    _check(lib().spx_field_init(enc.ref(), _dev(tables, h, "tables"), _dev(W1, h, "W1"), _dev(W2, h, "W2"),
+                                _dev(W3, h, "W3"), int(d_out), C.byref(out)), "spx_field_init")
+    return out
+
+
+def as_bytes(structs) -> bytes:
+    return b"".join(bytes(s) for s in structs)
+
+
+def spx_field_query_batched(fields_dev, nfields: int, segs_dev, nseg: int, total_tiles: int, stream=None) -> None:
+    """fields_dev / segs_dev: uint8 GPU tensors holding spx_field / spx_segment arrays."""
+    torch = _torch()
+    _check(lib().spx_field_query_batched(_dev(fields_dev, torch.uint8, "fields"), int(nfields),
+                                         _dev(segs_dev, torch.uint8, "segs"), int(nseg), int(total_tiles),
+                                         _stream(stream)), "spx_field_query_batched")
