@@ -147,25 +147,39 @@ class TrainStep:
 
 
 def time_steps(ts, steps, warmup):
+    """Whole-step time (events around the K steps) plus, from the library's
+    kernel trace of the same steps, every kernel's average duration and its
+    algorithmic bytes."""
     import torch
+    from paper_2311_15439_amd import spx
     for i in range(warmup):
         ts.step(i)
     torch.cuda.synchronize()
     K = len(ts.names)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(K + 1)] for _ in range(steps)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    trace = spx.Trace(capacity=32 * steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
-    for i in range(steps):
-        ts.step(warmup + i, evs[i])
+    with trace:
+        for i in range(steps):
+            ts.step(warmup + i, evs[i])
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(end)
     per = {n: float(np.mean([evs[i][k].elapsed_time(evs[i][k + 1]) for i in range(steps)]))
            for k, n in enumerate(ts.names)}
-    return total_ms / steps, per, wall
+    kern = {}
+    for name, nbytes, ms in trace.results():
+        k = kern.setdefault(name, [0.0, 0.0, 0])
+        k[0] += ms
+        k[1] += nbytes
+        k[2] += 1
+    kernels = {n: {"avg_ms": v[0] / v[2], "bytes_per_launch": v[1] / v[2], "launches_per_step": v[2] / steps}
+               for n, v in kern.items()}
+    return total_ms / steps, per, wall, kernels
 
 
 def time_encode_only(ts, reps=20):
@@ -225,6 +239,98 @@ def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
                       f"encode fwd and MLP fwd use {threads} OpenMP threads, the rest one thread"}
 
 
+def serving_bench(n_fields=8, n_requests=2000, warm=200, loads=(0.5, 0.8), train_steps=30):
+    """Serving: resident 3-D fields (n=3, L=16, T=2^19, F=2 binary16, MLP
+    32-64-64-4), each briefly trained on its own synthetic density; requests
+    of log-uniform size 2^8..2^20 points on a uniformly chosen field.  First
+    the saturation rate (requests submitted back to back), then Poisson
+    arrivals at fractions of it; latency is submit -> results in host
+    memory."""
+    import threading
+
+    import torch
+    from paper_2311_15439_amd import inputs, spx
+    from paper_2311_15439_amd.serve import GpuBackend, Server
+    from paper_2311_15439_amd.torch_ops import NeuralField, SimplexEncoding, TinyMLP
+
+    w = inputs.VOLUME_3D
+    descs, keep = [], []
+    train_pts = inputs.uniform_points(1 << 16, 3, 99)
+    tp = torch.from_numpy(train_pts).cuda()
+    for f in range(n_fields):
+        enc = SimplexEncoding(3, w.n_levels, w.log2_T, 2, n_min=w.n_min, growth=w.growth, seed=20 + f)
+        net = TinyMLP(32, 4, seed=40 + f)
+        field = NeuralField(enc, net)
+        tgt = torch.from_numpy(inputs.procedural_density(train_pts, 20 + f)).cuda()
+        opt = torch.optim.Adam(field.parameters(), lr=1e-2, betas=(0.9, 0.99), eps=1e-15)
+        for _ in range(train_steps):
+            loss = torch.mean((field(tp) - tgt) ** 2)
+            opt.zero_grad()
+            loss.backward()
+            opt.step()
+        enc.sync()
+        net.sync()
+        descs.append(spx.spx_field_init(enc.enc, enc.table_f16, *net._W16, 4))
+        keep.append((enc, net))
+    torch.cuda.synchronize()
+    pool = inputs.uniform_points(1 << 22, 3, 123)
+    rng = np.random.default_rng(30)
+
+    def make(k):
+        sizes = np.floor(2.0 ** rng.uniform(8, 20, k)).astype(int)
+        fields = rng.integers(0, n_fields, k)
+        starts = rng.integers(0, len(pool) - (1 << 20), k)
+        return [(int(f), pool[s:s + m]) for f, s, m in zip(fields, starts, sizes)]
+
+    be = GpuBackend(descs)
+    srv = Server(be, [3] * n_fields, [4] * n_fields, arena_bytes=512 << 20, chunk_points=1 << 18,
+                 batch_points=1 << 21).start()
+    try:
+        for f, p in make(warm):
+            srv.submit(f, p)
+        reqs = make(n_requests)
+        t0 = time.perf_counter()
+        rs = [srv.submit(f, p) for f, p in reqs]
+        for r in rs:
+            r.wait(120)
+        sat_s = time.perf_counter() - t0
+        pts_total = sum(len(p) for _, p in reqs)
+        sat = pts_total / sat_s
+        mean_m = pts_total / len(reqs)
+        out = {"fields": n_fields, "requests_per_load": n_requests, "mean_request_points": mean_m,
+               "saturation_points_per_s": sat, "saturation_requests_per_s": len(reqs) / sat_s, "loads": []}
+        for load in loads:
+            lam = load * sat / mean_m
+            reqs = make(n_requests)
+            gaps = rng.exponential(1.0 / lam, len(reqs))
+            submitted = []
+
+            def client():
+                t = time.perf_counter()
+                for (f, p), g in zip(reqs, gaps):
+                    t += g
+                    d = t - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    submitted.append(srv.submit(f, p))
+
+            th = threading.Thread(target=client)
+            t0 = time.perf_counter()
+            th.start()
+            th.join()
+            for r in submitted:
+                r.wait(120)
+            span = time.perf_counter() - t0
+            lat = np.array([r.latency for r in submitted]) * 1e3
+            out["loads"].append({"load": load, "offered_requests_per_s": lam,
+                                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                                 "points_per_s": sum(len(p) for _, p in reqs) / span})
+        out["batches"] = srv.batches
+    finally:
+        srv.stop()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +339,7 @@ def main():
     ap.add_argument("--workload", default="image-2d", choices=["image-2d", "volume-3d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -258,14 +365,18 @@ def main():
     ts = TrainStep(w, spx.SPX_SIMPLEX, batches, host_tables, weights, d_out)
     res = ts.res
     print("# timing simplex step", file=sys.stderr, flush=True)
-    ms, per, wall = time_steps(ts, args.steps, args.warmup)
+    ms, per, wall, kern = time_steps(ts, args.steps, args.warmup)
     enc_s = time_encode_only(ts)
     bytes_ = ts.algorithmic_bytes()
     per = {k: v for k, v in per.items() if bytes_.get(k, 0) > 0}
-    dom = max(per, key=per.get)
-    achieved = bytes_[dom] / (per[dom] * 1e-3) / 1e9
-    kernels = {k: {"avg_ms": round(v, 5), "algorithmic_GB_s": round(bytes_[k] / (v * 1e-3) / 1e9, 1)}
-               for k, v in per.items()}
+    # dominant single kernel of the step (total time per step), from the trace
+    dom = max(kern, key=lambda n: kern[n]["avg_ms"] * kern[n]["launches_per_step"])
+    achieved = kern[dom]["bytes_per_launch"] / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+    calls = {k: {"avg_ms": round(v, 5), "algorithmic_GB_s": round(bytes_[k] / (v * 1e-3) / 1e9, 1)}
+             for k, v in per.items()}
+    kernels = {n: {"avg_ms": round(v["avg_ms"], 5), "launches_per_step": v["launches_per_step"],
+                   "algorithmic_GB_s": round(v["bytes_per_launch"] / (v["avg_ms"] * 1e-3) / 1e9, 1)}
+               for n, v in sorted(kern.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches_per_step"])}
 
     grid = None
     if not args.no_grid:
@@ -273,13 +384,18 @@ def main():
         torch.cuda.empty_cache()
         tg = TrainStep(w, spx.SPX_GRID, batches, host_tables, weights, d_out)
         print("# timing grid step", file=sys.stderr, flush=True)
-        gms, gper, _ = time_steps(tg, max(5, args.steps // 2), 2)
+        gms, gper, _, gkern = time_steps(tg, max(5, args.steps // 2), 2)
         genc = time_encode_only(tg)
         gb = tg.algorithmic_bytes()
         grid = {"step_points_per_s": tg.N / (gms * 1e-3), "ms_per_step": gms,
                 "kernels_ms": {k: round(v, 5) for k, v in gper.items() if gb.get(k, 0) > 0}, "encode_only": genc}
         del tg
         torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serving:
+        print("# serving: training resident fields, then saturation and Poisson loads", file=sys.stderr, flush=True)
+        serving = serving_bench()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -303,12 +419,15 @@ def main():
         "config": {"workload": w.name + f", {w.n_points} points/step, MLP {w.n_levels * w.n_feat}-64-64-{d_out}",
                    "levels": res, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_ms": kern[dom]["avg_ms"], "bytes_per_launch": kern[dom]["bytes_per_launch"]},
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "calls": calls,
         "encode_only": {"simplex": enc_s, "grid": grid["encode_only"] if grid else None},
         "grid_baseline_step": ({"points_per_s": grid["step_points_per_s"], "ms_per_step": grid["ms_per_step"],
                                 "kernels_ms": grid["kernels_ms"]} if grid else None),
+        "serving": serving,
         "wall_s_timed": wall,
     }
     print(json.dumps(line), flush=True)

@@ -85,6 +85,25 @@ const char* spx_status_str(spx_status s);
 const char* spx_last_error(void);
 
 /*
+ * Kernel tracing (profiling aid).  While a trace is set on a thread, every
+ * kernel the library launches from that thread is bracketed by
+ * events[2i] / events[2i+1], recorded on its launch stream, and described
+ * by names[i] (a static string) and bytes[i] (the bytes the kernel must move
+ * by its own definition: inputs read plus outputs written).  Kernels beyond
+ * capacity are not recorded.  The caller creates the 2 * capacity events
+ * and reads the elapsed times after synchronising.  Pass NULL to stop.
+ */
+typedef struct {
+    hipEvent_t* events;   /* [2 * capacity] */
+    const char** names;   /* [capacity] */
+    double* bytes;        /* [capacity] */
+    int32_t capacity;
+    int32_t count;        /* kernels recorded so far (written by the library) */
+} spx_trace;
+
+spx_status spx_trace_set(spx_trace* trace);
+
+/*
  * Host helper: geometric level schedule N_l = floor(n_min * growth^l + 1e-6)
  * for l < L (the paper scales the unit cube per level, Sec. 5.1, without
  * fixing the schedule).  res_out: host [L].  Errors: SPX_EINVAL if

@@ -12,6 +12,27 @@
 #include "lookup.hpp"
 #include "spx_internal.h"
 
+namespace spx {
+
+static thread_local spx_trace* g_trace = nullptr;
+
+void trace_begin(hipStream_t s, const char* name, double bytes) {
+    spx_trace* t = g_trace;
+    if (!t || t->count >= t->capacity) return;
+    hipEventRecord(t->events[2 * t->count], s);
+    t->names[t->count] = name;
+    t->bytes[t->count] = bytes;
+}
+
+void trace_end(hipStream_t s) {
+    spx_trace* t = g_trace;
+    if (!t || t->count >= t->capacity) return;
+    hipEventRecord(t->events[2 * t->count + 1], s);
+    t->count += 1;
+}
+
+}  // namespace spx
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -115,6 +136,13 @@ spx_status check_points(int64_t N, const float* pts) {
 extern "C" {
 
 int32_t spx_abi_version(void) { return SPX_ABI_VERSION; }
+
+spx_status spx_trace_set(spx_trace* trace) {
+    if (trace && (trace->capacity < 0 || (trace->capacity > 0 && (!trace->events || !trace->names || !trace->bytes))))
+        return fail(SPX_EINVAL, "trace arrays missing");
+    spx::g_trace = trace;
+    return SPX_OK;
+}
 
 const char* spx_status_str(spx_status s) {
     switch (s) {

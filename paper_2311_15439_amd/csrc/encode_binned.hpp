@@ -381,21 +381,42 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
 template <class Tag, int D, int F, typename GT>
 hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
     const GT* d_out = (const GT*)c.d_out;
+    constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+    const double N = (double)c.N, gs = sizeof(GT), rec = sizeof(BinRec<F>);
+    const double counts = (double)p.W * p.B * 4.0;
+    const double recs = N * (p.l1 - p.l0 - p.P) * V * rec;  // in-box points emit no records at privatised levels
+    const double slots = (double)p.B * (1 << p.s_log2) * F;
+    trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
+    trace_end(c.stream);
     if (p.P > 0) {
         const int n = p.Dtot * F;
+        trace_begin(c.stream, "bin_coarse", N * (4.0 * D + p.P * F * gs) + (double)p.W * n * 4.0);
         bin_coarse_kernel<Tag, D, F, GT><<<p.W, kBinBlock, (size_t)n * sizeof(float), c.stream>>>(c.N, c.pts, d_out,
                                                                                                 c.lv, p);
+        trace_end(c.stream);
+        trace_begin(c.stream, "bin_coarse_reduce", ((double)p.W + 1.0) * n * 4.0);
         bin_coarse_reduce_kernel<<<(n + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, n);
+        trace_end(c.stream);
     }
+    trace_begin(c.stream, "bin_colscan", 2.0 * counts + 4.0 * p.B);
     bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
+    trace_end(c.stream);
+    trace_begin(c.stream, "bin_scan", 8.0 * p.B + 4.0);
     bin_scan_kernel<<<1, 1024, 0, c.stream>>>(p.B, totals, p.base);
+    trace_end(c.stream);
+    trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + recs);
     bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv, p);
+    trace_end(c.stream);
     const size_t lds = (size_t)(F << p.s_log2) * sizeof(float);
-    if (c.adam.param)
+    if (c.adam.param) {
+        trace_begin(c.stream, "bin_accum_adam", recs + slots * (c.adam.param_f16 ? 26.0 : 24.0));
         bin_accum_kernel<D, F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, nullptr, c.adam);
-    else
+    } else {
+        trace_begin(c.stream, "bin_accum", recs + slots * 8.0);
         bin_accum_kernel<D, F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, c.d_tables, c.adam);
+    }
+    trace_end(c.stream);
     return hipGetLastError();
 }
 

@@ -15,9 +15,14 @@ inline unsigned grid_for(int64_t N) {
     return (unsigned)(blocks < cap ? (blocks > 0 ? blocks : 1) : cap);
 }
 
+template <class Tag, int D>
+constexpr int vertices() { return Tag::simplex ? D + 1 : (1 << D); }
+
 template <class Tag, int D, int F>
 hipError_t fwd_dispatch_types(const EncodeCall& c) {
     dim3 g(grid_for(c.N)), b(kBlock);
+    const double per_pt = 4.0 * D + (double)c.lv.L * F * (vertices<Tag, D>() * (c.table_f16 ? 2 : 4) + (c.out_f16 ? 2 : 4));
+    trace_begin(c.stream, "encode_fwd", per_pt * (double)c.N);
     if (c.table_f16 && c.out_f16)
         encode_fwd_kernel<Tag, D, F, f16, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (f16*)c.out, c.lv);
     else if (c.table_f16)
@@ -26,16 +31,20 @@ hipError_t fwd_dispatch_types(const EncodeCall& c) {
         encode_fwd_kernel<Tag, D, F, float, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (f16*)c.out, c.lv);
     else
         encode_fwd_kernel<Tag, D, F, float, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (float*)c.out, c.lv);
+    trace_end(c.stream);
     return hipGetLastError();
 }
 
 template <class Tag, int D, int F>
 hipError_t bwd_dispatch_types(const EncodeCall& c) {
     dim3 g(grid_for(c.N)), b(kBlock);
+    const double per_pt = 4.0 * D + (double)c.lv.L * F * ((c.dout_f16 ? 2 : 4) + vertices<Tag, D>() * 8);
+    trace_begin(c.stream, "encode_bwd_atomic", per_pt * (double)c.N);
     if (c.dout_f16)
         encode_bwd_kernel<Tag, D, F, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.d_out, c.d_tables, c.lv);
     else
         encode_bwd_kernel<Tag, D, F, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.d_out, c.d_tables, c.lv);
+    trace_end(c.stream);
     return hipGetLastError();
 }
 
@@ -51,7 +60,9 @@ hipError_t dispatch_F(const EncodeCall& c) {
         }
     }
     if (c.op == EncodeOp::Debug) {
+        trace_begin(c.stream, "encode_debug", (4.0 * D + 8.0 * c.lv.L * vertices<Tag, D>()) * (double)c.N);
         encode_debug_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, c.idx, c.w, c.lv);
+        trace_end(c.stream);
         return hipGetLastError();
     }
     const bool fwd = c.op == EncodeOp::Forward;

@@ -150,7 +150,11 @@ hipError_t field_query(const spx_field* fields, int nfields, const spx_segment* 
     int64_t blocks = (waves + 3) / 4;
     const int64_t cap = 8192;
     blocks = blocks < cap ? (blocks > 0 ? blocks : 1) : cap;
+    // nominal bytes for 3-D fields with 4 outputs (the kernel reads the field
+    // descriptors on the device): point, 16 levels x 4 vertices x 4 bytes, output
+    trace_begin(s, "field_query", (double)total_tiles * 16.0 * (12.0 + 16.0 * 4.0 * 4.0 + 16.0));
     field_query_kernel<<<(unsigned)blocks, 256, 0, s>>>(fields, nfields, segs, nseg, total_tiles);
+    trace_end(s);
     return hipGetLastError();
 }
 

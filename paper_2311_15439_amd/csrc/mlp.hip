@@ -362,8 +362,10 @@ hipError_t fwd_impl(const MlpCall& c) {
     int64_t blocks = (tiles + 3) / 4;
     const int64_t cap = 4096;
     unsigned g = (unsigned)(blocks < cap ? (blocks > 0 ? blocks : 1) : cap);
+    trace_begin(c.stream, "mlp_fwd", (double)c.N * (2.0 * DIN + 4.0 * c.d_out) + 2.0 * (H * DIN + H * H + H * c.d_out));
     mlp_fwd_kernel<DIN><<<g, 256, 0, c.stream>>>(c.N, (const _Float16*)c.x, (const _Float16*)c.W1,
                                                  (const _Float16*)c.W2, (const _Float16*)c.W3, c.d_out, c.y);
+    trace_end(c.stream);
     return hipGetLastError();
 }
 
@@ -372,12 +374,17 @@ hipError_t bwd_impl(const MlpCall& c) {
     using Lay = BwdLayout<DIN>;
     const int g = bwd_groups(c.N);
     float* part = (float*)c.workspace;
+    trace_begin(c.stream, "mlp_bwd",
+                (double)c.N * (2.0 * DIN + 4.0 * c.d_out + (c.d_x ? 4.0 * DIN : 0.0)) + (double)g * Lay::PARTIAL * 4.0);
     mlp_bwd_kernel<DIN><<<g, 256, Lay::LDS_BYTES, c.stream>>>(c.N, (const _Float16*)c.x, (const _Float16*)c.W1,
                                                               (const _Float16*)c.W2, (const _Float16*)c.W3,
                                                               c.d_out, c.d_y, c.d_x, part);
+    trace_end(c.stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    trace_begin(c.stream, "mlp_reduce", ((double)g + 1.0) * Lay::PARTIAL * 4.0);
     mlp_reduce_kernel<DIN><<<(Lay::PARTIAL + 63) / 64, 256, 0, c.stream>>>(part, g, c.d_out, c.dW1, c.dW2, c.dW3);
+    trace_end(c.stream);
     return hipGetLastError();
 }
 

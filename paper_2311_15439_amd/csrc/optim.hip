@@ -52,19 +52,25 @@ __global__ __launch_bounds__(kBlock) void mse_grad_kernel(int64_t n, const float
 }  // namespace
 
 hipError_t mse_grad(int64_t n, const float* y, const float* target, float* d_y, float scale, hipStream_t s) {
+    trace_begin(s, "mse_grad", 12.0 * (double)n);
     mse_grad_kernel<<<blocks_for(n, 4), kBlock, 0, s>>>(n, y, target, d_y, scale);
+    trace_end(s);
     return hipGetLastError();
 }
 
 hipError_t cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t s) {
+    trace_begin(s, "cast_f32_f16", 6.0 * (double)n);
     cast_kernel<<<blocks_for(n, 4), kBlock, 0, s>>>(n, src, (_Float16*)dst);
+    trace_end(s);
     return hipGetLastError();
 }
 
 hipError_t adam_step(int64_t n, float* param, float* grad, float* m, float* v, uint16_t* param_f16, float lr,
                      float beta1, float beta2, float eps, float bc1, float bc2, int zero_grad, hipStream_t s) {
+    trace_begin(s, "adam", (double)n * (28.0 + (zero_grad ? 4.0 : 0.0) + (param_f16 ? 2.0 : 0.0)));
     adam_kernel<<<blocks_for(n, 4), kBlock, 0, s>>>(n, param, grad, m, v, (_Float16*)param_f16, lr, beta1, beta2, eps,
                                                     1.0f / bc1, 1.0f / bc2, zero_grad);
+    trace_end(s);
     return hipGetLastError();
 }
 

@@ -9,6 +9,10 @@
 
 namespace spx {
 
+// Tracing hooks (no-ops unless a trace is set on the calling thread).
+void trace_begin(hipStream_t s, const char* name, double bytes);
+void trace_end(hipStream_t s);
+
 struct SimplexTag { static constexpr bool simplex = true; };
 struct GridTag { static constexpr bool simplex = false; };
 

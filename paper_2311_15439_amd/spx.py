@@ -47,6 +47,11 @@ class spx_segment(C.Structure):
                 ("field", C.c_int32), ("pad", C.c_int32)]
 
 
+class spx_trace(C.Structure):
+    _fields_ = [("events", C.c_void_p), ("names", C.c_void_p), ("bytes", C.c_void_p), ("capacity", C.c_int32),
+                ("count", C.c_int32)]
+
+
 class spx_mlp(C.Structure):
     _fields_ = [("d_in", C.c_int32), ("hidden", C.c_int32), ("d_out", C.c_int32)]
 
@@ -56,6 +61,7 @@ _SIGNATURES = {
     "spx_abi_version": (C.c_int32, []),
     "spx_status_str": (C.c_char_p, [C.c_int]),
     "spx_last_error": (C.c_char_p, []),
+    "spx_trace_set": (C.c_int, [_P]),
     "spx_level_resolutions": (C.c_int, [C.c_double, C.c_double, C.c_int32, _P]),
     "spx_level_scales": (C.c_int, [_P, _P]),
     "spx_hash_primes": (C.c_int, [_P]),
@@ -85,6 +91,10 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_15439_amd.build`")
+        try:  # load torch's HIP runtime first so the library and torch share one runtime
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(L, name)
@@ -378,3 +388,43 @@ def spx_field_query_batched(fields_dev, nfields: int, segs_dev, nseg: int, total
     _check(lib().spx_field_query_batched(_dev(fields_dev, torch.uint8, "fields"), int(nfields),
                                          _dev(segs_dev, torch.uint8, "segs"), int(nseg), int(total_tiles),
                                          _stream(stream)), "spx_field_query_batched")
+
+
+# --------------------------------------------------------------- tracing
+
+class Trace:
+    """Per-kernel timing of everything the library launches on this thread
+    inside ``with Trace(...)``: name, algorithmic bytes and duration (ms)
+    from HIP events on each kernel's launch stream."""
+
+    def __init__(self, capacity: int = 256):
+        torch = _torch()
+        self.capacity = capacity
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * capacity)]
+        s = torch.cuda.current_stream()
+        for e in self.events:  # create the underlying HIP events
+            e.record(s)
+        torch.cuda.synchronize()
+        self._ev = (C.c_void_p * (2 * capacity))(*[e.cuda_event for e in self.events])
+        self._names = (C.c_char_p * capacity)()
+        self._bytes = (C.c_double * capacity)()
+        self.t = spx_trace()
+        self.t.events = C.cast(self._ev, C.c_void_p)
+        self.t.names = C.cast(self._names, C.c_void_p)
+        self.t.bytes = C.cast(self._bytes, C.c_void_p)
+        self.t.capacity = capacity
+
+    def __enter__(self):
+        self.t.count = 0
+        _check(lib().spx_trace_set(C.byref(self.t)), "spx_trace_set")
+        return self
+
+    def __exit__(self, *exc):
+        lib().spx_trace_set(None)
+        return False
+
+    def results(self):
+        """[(name, bytes, ms)] in launch order (synchronises)."""
+        _torch().cuda.synchronize()
+        return [(self._names[i].decode(), float(self._bytes[i]), self.events[2 * i].elapsed_time(self.events[2 * i + 1]))
+                for i in range(self.t.count)]
