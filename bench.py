@@ -30,6 +30,71 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 
 
+COPY_ELEMS = 1 << 26  # calibration copy: 256 MiB read, 128 MiB written
+TRAFFIC_FILE = os.path.join("profiles", "bin_accum_adam_image2d_traffic.json")
+# kernels whose counters the traffic file holds, and the sources that define them
+TRAFFIC_KERNELS = {"bin_accum_adam": ("bin_accum_kernel", "true")}
+TRAFFIC_SOURCES = ["paper_2311_15439_amd/csrc/encode_binned.hpp", "paper_2311_15439_amd/csrc/spx_internal.h",
+                   "paper_2311_15439_amd/csrc/encode_simplex.hip"]
+
+
+def _sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _counter_rows(path):
+    """(kernel name, counter value in KiB) per dispatch of a rocprofv3 --pmc CSV."""
+    import csv
+    out = []
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def write_traffic(fetch_csv, write_csv):
+    """HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
+    counter runs, each scaled by what the counter reads for the calibration
+    copy of known size (the last cast kernel dispatch)."""
+    res = {"sources_sha256": _sources_digest(), "copy_elems": COPY_ELEMS, "kernels": {}}
+    known = {"FETCH_SIZE": COPY_ELEMS * 4 / 1024.0, "WRITE_SIZE": COPY_ELEMS * 2 / 1024.0}
+    rows = {"FETCH_SIZE": _counter_rows(fetch_csv), "WRITE_SIZE": _counter_rows(write_csv)}
+    factor = {}
+    for c, rr in rows.items():
+        copy = [v for k, v in rr if "cast_kernel" in k]
+        factor[c] = copy[-1] / known[c]
+    res["factor"] = factor
+    for name, (sym, tmpl) in TRAFFIC_KERNELS.items():
+        entry = {}
+        for c, rr in rows.items():
+            vals = [v for k, v in rr if sym in k and tmpl in k.split(sym, 1)[1]]
+            entry[c + "_KiB_raw"] = vals[-1]
+            entry[c + "_bytes"] = vals[-1] * 1024.0 / factor[c]
+        entry["bytes"] = entry["FETCH_SIZE_bytes"] + entry["WRITE_SIZE_bytes"]
+        res["kernels"][name] = entry
+    with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch measured by the counter runs, or None if there is
+    no measurement for this kernel or its sources changed since it was taken."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("sources_sha256") != _sources_digest() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["bytes"]
+
+
 def _workload(name):
     from paper_2311_15439_amd import inputs
     return {"image-2d": inputs.IMAGE_2D, "volume-3d": inputs.VOLUME_3D}[name]
@@ -52,14 +117,15 @@ def _targets(w, pts, batch):
 class TrainStep:
     """All device buffers of one training step; launches only library kernels."""
 
-    def __init__(self, w, cell, batches, host_tables, weights, d_out, fused=True):
+    def __init__(self, w, cell, batches, host_tables, weights, d_out, fused=True, equal_memory=False):
         import torch
         from paper_2311_15439_amd import spx
         self.torch, self.spx = torch, spx
         dev = "cuda"
         self.w = w
         self.res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
-        self.enc = spx.Encoding(w.n_dims, self.res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16, cell=cell)
+        self.enc = spx.Encoding(w.n_dims, self.res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16, cell=cell,
+                                equal_memory=equal_memory)
         self.N = w.n_points
         self.batches = [(torch.from_numpy(p).to(dev), torch.from_numpy(t).to(dev)) for p, t in batches]
         self.master = torch.from_numpy(host_tables.astype(np.float32)).to(dev)
@@ -123,7 +189,8 @@ class TrainStep:
         rec(7)
 
     def algorithmic_bytes(self):
-        """Bytes each kernel must move per launch."""
+        """Bytes each kernel must move per launch (what the method reads and
+        writes, once each)."""
         w, N = self.w, self.N
         n, L, F = w.n_dims, w.n_levels, w.n_feat
         V = (1 << n) if self.enc.cell == self.spx.SPX_GRID else n + 1
@@ -205,6 +272,128 @@ def time_encode_only(ts, reps=20):
     b = e[1].elapsed_time(e[2]) / reps
     return {"fwd_ms": f, "bwd_ms": b, "fwd_points_per_s": ts.N / (f * 1e-3),
             "fwd_bwd_points_per_s": ts.N / ((f + b) * 1e-3)}
+
+
+def _quantiles(ms):
+    q = np.percentile(np.asarray(ms), [10, 50, 90])
+    return {"p10_ms": float(q[0]), "median_ms": float(q[1]), "p90_ms": float(q[2])}
+
+
+def time_encode_sweep(reps=30, warm=5):
+    """Encoding alone, simplex vs the 2^n grid on identical points and tables:
+    the volume workload (n=3, L=16, T=2^19, 2^21 ray samples) and the
+    dimension sweep (n=2..6, L=8, T=2^20, 2^20 uniform points).  Forward, and
+    forward + binned adjoint (with the gradient clearing, timed on its own
+    too); median and p10/p90 over per-repetition events."""
+    import torch
+    from paper_2311_15439_amd import inputs, spx
+    dev = "cuda"
+    out = {}
+    wls = [inputs.VOLUME_3D] + [inputs.sweep_workload(n) for n in range(2, 7)]
+    for w in wls:
+        print(f"# encode sweep: {w.name}", file=sys.stderr, flush=True)
+        if w.name.startswith("volume"):
+            p = inputs.ray_points(w.n_points // 256, 256, w.seed_points)
+        else:
+            p = inputs.uniform_points(w.n_points, w.n_dims, w.seed_points)
+        N = p.shape[0]
+        pts = torch.from_numpy(p).to(dev)
+        tab = torch.from_numpy(inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables,
+                                             True)).to(dev)
+        D = w.n_levels * w.n_feat
+        dout = torch.from_numpy(inputs.gradients(N, D, w.seed_points + 50)).to(dev)
+        feats = torch.empty((N, D), dtype=torch.float16, device=dev)
+        grad = torch.zeros(tab.shape, dtype=torch.float32, device=dev)
+        res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
+        row = {"points": N}
+        for cell, cname in ((spx.SPX_SIMPLEX, "simplex"), (spx.SPX_GRID, "grid")):
+            enc = spx.Encoding(w.n_dims, res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16, cell=cell)
+            ws = torch.empty(spx.spx_encode_bwd_workspace(enc, N), dtype=torch.uint8, device=dev)
+            for _ in range(warm):
+                spx.spx_encode_fwd(enc, pts, tab, feats)
+                grad.zero_()
+                spx.spx_encode_bwd(enc, pts, dout, grad, ws)
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+            torch.cuda.synchronize()
+            for r in range(reps):
+                ev[r][0].record()
+                spx.spx_encode_fwd(enc, pts, tab, feats)
+                ev[r][1].record()
+                grad.zero_()
+                ev[r][2].record()
+                spx.spx_encode_bwd(enc, pts, dout, grad, ws)
+                ev[r][3].record()
+            torch.cuda.synchronize()
+            f = [e[0].elapsed_time(e[1]) for e in ev]
+            z = [e[1].elapsed_time(e[2]) for e in ev]
+            b = [e[2].elapsed_time(e[3]) for e in ev]
+            t = [e[0].elapsed_time(e[3]) for e in ev]
+            fq, tq = _quantiles(f), _quantiles(t)
+            row[cname] = {"fwd": fq, "zero_grad": _quantiles(z), "bwd": _quantiles(b), "fwd_bwd": tq,
+                          "fwd_points_per_s": N / (fq["median_ms"] * 1e-3),
+                          "fwd_bwd_points_per_s": N / (tq["median_ms"] * 1e-3)}
+            del ws
+        row["simplex_speedup_fwd"] = row["grid"]["fwd"]["median_ms"] / row["simplex"]["fwd"]["median_ms"]
+        row["simplex_speedup_fwd_bwd"] = row["grid"]["fwd_bwd"]["median_ms"] / row["simplex"]["fwd_bwd"]["median_ms"]
+        out[w.name] = row
+        del pts, tab, dout, feats, grad
+        torch.cuda.empty_cache()
+    return out
+
+
+def equal_accuracy(w, host_tables, weights, d_out, steps=2000, n_train=6):
+    """Accuracy at equal memory: train the image field with the simplex
+    encoding (equal-memory level scaling on) and with the 2^n grid for the
+    same number of steps on the same batches, then compare the PSNR on a
+    held-out batch of pixel positions."""
+    import torch
+    from paper_2311_15439_amd import spx
+    batches = []
+    for b in range(n_train + 1):
+        p = _points(w, 100 + b)
+        batches.append((p, _targets(w, p, 100 + b)))
+    held_p, held_t = batches.pop()
+    out = {"steps": steps, "train_batches": n_train, "points_per_step": w.n_points}
+    for cell, em, name in ((spx.SPX_SIMPLEX, True, "simplex_equal_memory"), (spx.SPX_GRID, False, "grid")):
+        print(f"# equal accuracy: training {name} for {steps} steps", file=sys.stderr, flush=True)
+        ts = TrainStep(w, cell, batches, host_tables, weights, d_out, equal_memory=em)
+        for i in range(steps):
+            ts.step(i)
+        hp = torch.from_numpy(held_p).to("cuda")
+        ht = torch.from_numpy(held_t).to("cuda")
+        spx.spx_encode_fwd(ts.enc, hp, ts.tab16, ts.feats)
+        spx.spx_mlp_fwd(ts.mlp, ts.feats, *ts.Wv, ts.y)
+        mse = torch.mean((ts.y.clamp(0, 1) - ht) ** 2).item()
+        out[name] = {"psnr_db": 10.0 * np.log10(1.0 / mse), "mse": mse}
+        del ts
+        torch.cuda.empty_cache()
+    out["simplex_minus_grid_db"] = out["simplex_equal_memory"]["psnr_db"] - out["grid"]["psnr_db"]
+    return out
+
+
+def time_stream_reference(ts, reps=10):
+    """Plain streaming kernels over the whole table, for the practical HBM
+    ceiling: the unfused Adam (36 bytes per parameter) and the binary16 copy
+    (6 bytes per parameter)."""
+    import torch
+    spx = ts.spx
+    P = ts.master.numel()
+    kw = dict(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, step=1, zero_grad=True)
+    for _ in range(2):
+        spx.spx_adam_step(ts.master, ts.grad, ts.m, ts.v, ts.tab16, **kw)
+        spx.spx_cast_f32_f16(ts.master.view(-1), ts.tab16.view(-1))
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        spx.spx_adam_step(ts.master, ts.grad, ts.m, ts.v, ts.tab16, **kw)
+    e[1].record()
+    for _ in range(reps):
+        spx.spx_cast_f32_f16(ts.master.view(-1), ts.tab16.view(-1))
+    e[2].record()
+    torch.cuda.synchronize()
+    a = e[0].elapsed_time(e[1]) / reps
+    c = e[1].elapsed_time(e[2]) / reps
+    return {"adam_ms": a, "adam_GB_s": P * 36 / (a * 1e-3) / 1e9, "cast_ms": c, "cast_GB_s": P * 6 / (c * 1e-3) / 1e9}
 
 
 def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
@@ -340,10 +529,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the volume / dimension-sweep encoding timings")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the equal-memory accuracy comparison")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="run two training steps and a binary32->binary16 copy of 2^26 elements, then exit "
+                         "(the program profiled by the rocprofv3 --pmc traffic runs)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter CSVs of the two --pmc runs into " + TRAFFIC_FILE + " and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding the tables by level over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -364,9 +563,20 @@ def main():
 
     ts = TrainStep(w, spx.SPX_SIMPLEX, batches, host_tables, weights, d_out)
     res = ts.res
+    if args.pmc_pass:
+        for b in range(2):
+            ts.step(b)
+        torch.cuda.synchronize()
+        src = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda")
+        dst = torch.empty(COPY_ELEMS, dtype=torch.float16, device="cuda")
+        spx.spx_cast_f32_f16(src, dst)
+        torch.cuda.synchronize()
+        print("# pmc pass done", file=sys.stderr, flush=True)
+        return
     print("# timing simplex step", file=sys.stderr, flush=True)
     ms, per, wall, kern = time_steps(ts, args.steps, args.warmup)
     enc_s = time_encode_only(ts)
+    stream = time_stream_reference(ts)
     bytes_ = ts.algorithmic_bytes()
     per = {k: v for k, v in per.items() if bytes_.get(k, 0) > 0}
     # dominant single kernel of the step (total time per step), from the trace
@@ -391,6 +601,14 @@ def main():
                 "kernels_ms": {k: round(v, 5) for k, v in gper.items() if gb.get(k, 0) > 0}, "encode_only": genc}
         del tg
         torch.cuda.empty_cache()
+
+    accuracy = None
+    if not args.no_accuracy and w.name.startswith("image"):
+        accuracy = equal_accuracy(w, host_tables, weights, d_out)
+
+    sweep = None
+    if not args.no_sweep:
+        sweep = time_encode_sweep()
 
     serving = None
     if not args.no_serving:
@@ -419,7 +637,7 @@ def main():
         "config": {"workload": w.name + f", {w.n_points} points/step, MLP {w.n_levels * w.n_feat}-64-64-{d_out}",
                    "levels": res, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "avg_ms": kern[dom]["avg_ms"], "bytes_per_launch": kern[dom]["bytes_per_launch"]},
         "cpu_baseline": cpu,
         "kernels": kernels,
@@ -427,6 +645,9 @@ def main():
         "encode_only": {"simplex": enc_s, "grid": grid["encode_only"] if grid else None},
         "grid_baseline_step": ({"points_per_s": grid["step_points_per_s"], "ms_per_step": grid["ms_per_step"],
                                 "kernels_ms": grid["kernels_ms"]} if grid else None),
+        "stream_reference": stream,
+        "encode_sweep": sweep,
+        "equal_accuracy": accuracy,
         "serving": serving,
         "wall_s_timed": wall,
     }

@@ -57,11 +57,10 @@ double orc_equal_memory_factor(int n) {
     return pow((double)n + 1.0, (double)(n - 1) / (2.0 * (double)n));
 }
 
-/* Geometric level schedule N_l = floor(N_min * b^l + 1e-6).  The paper only
- * says the cube is divided "accordingly to each level" (Sec. 5.1); the
+/* Geometric level schedule N_l = floor(N_min * b^l + 1e-6).  Sec. 5.1 only
+ * states that each level divides the cube at its own resolution; the
  * geometric progression and the 1e-6 guard (so that the top level of a
- * schedule given by its two ends lands on the integer end) are this build's
- * reading. */
+ * schedule given by its two ends lands on the integer end) are a reading. */
 void orc_level_resolutions(double n_min, double growth, int L, int32_t* res_out) {
     for (int l = 0; l < L; ++l) res_out[l] = (int32_t)floor(n_min * pow(growth, (double)l) + 1e-6);
 }

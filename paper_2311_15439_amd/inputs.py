@@ -38,7 +38,8 @@ def growth_from_ends(n_min: float, n_max: float, L: int) -> float:
     return (n_max / n_min) ** (1.0 / (L - 1))
 
 
-# Configurations (sizes as stated for the workloads).
+# Workloads: the image fit, the volume, and the dimension sweep, at the
+# sizes the paper's experiments use (Sec. 6), with synthetic contents.
 PLAIN_2D = Workload("plain-2d n=2 L=4 T=2^14 F=2 f32", 2, 4, 14, 2, False, 16.0, 1.5, 1 << 16, 1.0, 1, 2)
 IMAGE_2D = Workload("image-2d n=2 L=16 T=2^22 F=2 f16", 2, 16, 22, 2, True, 16.0,
                     growth_from_ends(16, 1 << 15, 16), 1 << 20, 1e-4, 3, 5)
