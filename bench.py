@@ -289,11 +289,13 @@ def time_encode_sweep(reps=30, warm=5):
     from paper_2311_15439_amd import inputs, spx
     dev = "cuda"
     out = {}
-    wls = [inputs.VOLUME_3D] + [inputs.sweep_workload(n) for n in range(2, 7)]
+    wls = [inputs.IMAGE_2D, inputs.VOLUME_3D] + [inputs.sweep_workload(n) for n in range(2, 7)]
     for w in wls:
         print(f"# encode sweep: {w.name}", file=sys.stderr, flush=True)
         if w.name.startswith("volume"):
             p = inputs.ray_points(w.n_points // 256, 256, w.seed_points)
+        elif w.name.startswith("image"):
+            p = inputs.pixel_points(w.n_points, w.seed_points)
         else:
             p = inputs.uniform_points(w.n_points, w.n_dims, w.seed_points)
         N = p.shape[0]
@@ -310,28 +312,40 @@ def time_encode_sweep(reps=30, warm=5):
             enc = spx.Encoding(w.n_dims, res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16, cell=cell)
             ws = torch.empty(spx.spx_encode_bwd_workspace(enc, N), dtype=torch.uint8, device=dev)
             for _ in range(warm):
+                spx.spx_encode_gather_twin(enc, pts, tab, feats)
                 spx.spx_encode_fwd(enc, pts, tab, feats)
                 grad.zero_()
                 spx.spx_encode_bwd(enc, pts, dout, grad, ws)
-            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
             torch.cuda.synchronize()
             for r in range(reps):
                 ev[r][0].record()
-                spx.spx_encode_fwd(enc, pts, tab, feats)
+                spx.spx_encode_gather_twin(enc, pts, tab, feats)
                 ev[r][1].record()
-                grad.zero_()
+                spx.spx_encode_fwd(enc, pts, tab, feats)
                 ev[r][2].record()
-                spx.spx_encode_bwd(enc, pts, dout, grad, ws)
+                grad.zero_()
                 ev[r][3].record()
+                spx.spx_encode_bwd(enc, pts, dout, grad, ws)
+                ev[r][4].record()
             torch.cuda.synchronize()
-            f = [e[0].elapsed_time(e[1]) for e in ev]
-            z = [e[1].elapsed_time(e[2]) for e in ev]
-            b = [e[2].elapsed_time(e[3]) for e in ev]
-            t = [e[0].elapsed_time(e[3]) for e in ev]
-            fq, tq = _quantiles(f), _quantiles(t)
+            tw = [e[0].elapsed_time(e[1]) for e in ev]
+            f = [e[1].elapsed_time(e[2]) for e in ev]
+            z = [e[2].elapsed_time(e[3]) for e in ev]
+            b = [e[3].elapsed_time(e[4]) for e in ev]
+            t = [e[1].elapsed_time(e[4]) for e in ev]
+            fq, tq, wq = _quantiles(f), _quantiles(t), _quantiles(tw)
+            V = enc.n_vertices
+            gathers = N * w.n_levels * V
             row[cname] = {"fwd": fq, "zero_grad": _quantiles(z), "bwd": _quantiles(b), "fwd_bwd": tq,
+                          "gather_twin": wq,
                           "fwd_points_per_s": N / (fq["median_ms"] * 1e-3),
-                          "fwd_bwd_points_per_s": N / (tq["median_ms"] * 1e-3)}
+                          "fwd_bwd_points_per_s": N / (tq["median_ms"] * 1e-3),
+                          "twin_gathers_per_s": gathers / (wq["median_ms"] * 1e-3),
+                          # fraction of the gather roofline: the twin's rate is the ceiling for one
+                          # gather per vertex and level; forward + adjoint touch every row twice
+                          "fwd_gather_frac": wq["median_ms"] / fq["median_ms"],
+                          "fwd_bwd_gather_frac": 2.0 * wq["median_ms"] / tq["median_ms"]}
             del ws
         row["simplex_speedup_fwd"] = row["grid"]["fwd"]["median_ms"] / row["simplex"]["fwd"]["median_ms"]
         row["simplex_speedup_fwd_bwd"] = row["grid"]["fwd_bwd"]["median_ms"] / row["simplex"]["fwd_bwd"]["median_ms"]
@@ -622,8 +636,11 @@ def main():
 
     value = w.n_points / (ms * 1e-3)
     line = {
-        "metric": "encoded points/s, training step (fwd+bwd+optimizer), simplex hash encoding",
+        "metric": "encoded points/s fwd & fwd+bwd, simplex vs 2^n-grid same GPU; serving p50/p99 ms",
         "value": value,
+        "value_is": ("points/s of the whole simplex training step (encode fwd, MLP fwd, loss gradient, MLP bwd, "
+                     "encode adjoint fused with Adam on the tables, Adam on the MLP) on the image workload; "
+                     "fwd-only, fwd+bwd and grid figures are under encode_sweep, grid_baseline_step, serving"),
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,

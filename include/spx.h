@@ -212,6 +212,24 @@ spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* 
 spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts, uint32_t* idx,
                             float* w, hipStream_t stream);
 
+/*
+ * Gather twin: a measurement reference for the forward, not part of the
+ * method.  It streams the same points, finds the same cell at every level
+ * and gathers the same number of table rows with the same per-level
+ * locality (n+1 rows for the simplex, 2^n for the grid), but the simplex
+ * walk takes the axes in index order (no sorting of the fractions) and the
+ * rows are summed without weights.  Its throughput is the gather rate the
+ * memory system sustains on the forward's access pattern; the forward's
+ * rate divided by it is the forward's fraction of that gather roofline.
+ *   tables  device [L][T][2] binary16 (n_feat must be 2, table_dtype
+ *           SPX_F16), 4-byte aligned.
+ *   out     device [N][L*2] binary16, 4-byte aligned: per level, the
+ *           unweighted sum of the gathered rows.
+ * Other feature counts or table types return SPX_EUNSUPPORTED.
+ */
+spx_status spx_encode_gather_twin(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
+                                  void* out, hipStream_t stream);
+
 /* Round-to-nearest-even binary32 -> binary16 copy of n elements (device,
  * src 4-byte and dst 2-byte aligned). */
 spx_status spx_cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t stream);

@@ -202,6 +202,24 @@ spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, 
     return from_hip(run(enc, c), "spx_encode_fwd launch");
 }
 
+spx_status spx_encode_gather_twin(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
+                                  void* out, hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (enc->n_feat != 2 || enc->table_dtype != SPX_F16)
+        return fail(SPX_EUNSUPPORTED, "the gather twin covers binary16 tables with n_feat = 2");
+    if (N == 0) return SPX_OK;
+    if (!tables || !out) return fail(SPX_EINVAL, "tables or out is NULL");
+    if (!aligned(tables, 4) || !aligned(out, 4)) return fail(SPX_EALIGN, "tables/out not 4-byte aligned");
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::Twin;
+    c.out_f16 = true;
+    c.tables = tables;
+    c.out = out;
+    return from_hip(run(enc, c), "spx_encode_gather_twin launch");
+}
+
 spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* bytes) {
     spx_status st = check_encoding(enc);
     if (st) return st;

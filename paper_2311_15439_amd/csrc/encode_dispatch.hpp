@@ -59,6 +59,14 @@ hipError_t dispatch_F(const EncodeCall& c) {
             default: return hipErrorInvalidValue;
         }
     }
+    if (c.op == EncodeOp::Twin) {
+        if (c.F != 2 || !c.table_f16 || !c.out_f16) return hipErrorInvalidValue;
+        trace_begin(c.stream, "encode_twin", (4.0 * D + (double)c.lv.L * 2 * (vertices<Tag, D>() * 2 + 2)) * (double)c.N);
+        encode_twin_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables,
+                                                                                     (f16*)c.out, c.lv);
+        trace_end(c.stream);
+        return hipGetLastError();
+    }
     if (c.op == EncodeOp::Debug) {
         trace_begin(c.stream, "encode_debug", (4.0 * D + 8.0 * c.lv.L * vertices<Tag, D>()) * (double)c.N);
         encode_debug_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, c.idx, c.w, c.lv);

@@ -175,6 +175,65 @@ __global__ __launch_bounds__(kBlock) void encode_fwd_kernel(int64_t N, const flo
     }
 }
 
+// ---- gather twin (measurement reference) -------------------------------
+// The forward's memory traffic without its arithmetic: the same point stream,
+// the same cells and the same number of hashed rows per level (n + 1 for
+// the simplex, 2^n for the grid) with the same per-level locality, but the
+// simplex walk takes the axes in fixed order (no ranking) and the rows are
+// summed without weights.  Binary16 tables with F = 2, binary16 output.
+template <int D>
+__device__ __forceinline__ void twin_simplex_slots(const float (&y)[D], float sigma, uint32_t mask,
+                                                   uint32_t (&h)[D + 1]) {
+#pragma clang fp contract(off)
+    uint32_t a[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) a[i] = (uint32_t)(int32_t)floorf(y[i] * sigma) * hash_prime(i);
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        uint32_t hk = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) hk ^= i < k ? a[i] + hash_prime(i) : a[i];
+        h[k] = hk & mask;
+    }
+}
+
+template <class Tag, int D>
+__global__ __launch_bounds__(kBlock) void encode_twin_kernel(int64_t N, const float* __restrict__ pts,
+                                                             const f16* __restrict__ tables, f16* __restrict__ out,
+                                                             LevelArgs lv) {
+    const uint32_t mask = lv.mask;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        f16* __restrict__ orow = out + pt * (int64_t)(lv.L * 2);
+#pragma unroll 4
+        for (int l = 0; l < lv.L; ++l) {
+            const f16* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * 2);
+            float acc[2] = {0.0f, 0.0f};
+            auto add = [&](const auto& h) {
+                constexpr int K = sizeof(h) / sizeof(uint32_t);
+                float v[K][2];
+#pragma unroll
+                for (int k = 0; k < K; ++k) RowIO<f16, 2>::load(tab + (size_t)h[k] * 2, v[k]);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    acc[0] += v[k][0];
+                    acc[1] += v[k][1];
+                }
+            };
+            if constexpr (Tag::simplex) {
+                uint32_t h[D + 1];
+                twin_simplex_slots<D>(y, lv.sigma[l], mask, h);
+                add(h);
+            } else {
+                visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto&, int) { add(h); });
+            }
+            RowIO<f16, 2>::store(orow + l * 2, acc);
+        }
+    }
+}
+
 // ---- adjoint ------------------------------------------------------------
 
 template <class Tag, int D, int F, typename GT>

@@ -71,6 +71,7 @@ _SIGNATURES = {
     "spx_encode_bwd_adam": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_float, C.c_float,
                                       C.c_float, C.c_float, C.c_int64, _P, C.c_size_t, _P]),
     "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
+    "spx_encode_gather_twin": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_cast_f32_f16": (C.c_int, [C.c_int64, _P, _P, _P]),
     "spx_adam_step": (C.c_int, [C.c_int64, _P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
                                 C.c_float, C.c_int64, C.c_int32, _P]),
@@ -288,6 +289,20 @@ def spx_encode_debug(enc: Encoding, pts, idx=None, w=None, stream=None) -> None:
                                   None if idx is None else _dev(idx, torch.int32, "idx"),
                                   None if w is None else _dev(w, torch.float32, "w"), _stream(stream)),
            "spx_encode_debug")
+
+
+def spx_encode_gather_twin(enc: Encoding, pts, tables, out, stream=None) -> None:
+    """Measurement reference: the forward's gathers in fixed walk order,
+    summed without weights.  tables [L, T, 2] float16, out [N, 2L] float16."""
+    torch = _torch()
+    N = pts.shape[0]
+    if pts.shape != (N, enc.n_dims) or tuple(tables.shape) != enc.table_shape:
+        raise ValueError("pts or tables shape does not match the encoding")
+    if tuple(out.shape) != (N, enc.n_levels * enc.n_feat):
+        raise ValueError("out shape must be [N, L*F]")
+    _check(lib().spx_encode_gather_twin(enc.ref(), N, _dev(pts, torch.float32, "pts"),
+                                        _dev(tables, torch.float16, "tables"), _dev(out, torch.float16, "out"),
+                                        _stream(stream)), "spx_encode_gather_twin")
 
 
 # --------------------------------------------------------------- elementwise
