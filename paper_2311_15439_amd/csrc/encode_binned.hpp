@@ -42,6 +42,30 @@ struct alignas(F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64) BinRec {
     float v[F];
 };
 
+// Record store that bypasses the caches' write-back: records are read only
+// by the next kernel, and dirty lines left behind in L2 would be written back
+// while that kernel streams the table state.  Only the staged scatter uses it,
+// where a wave's stores form contiguous runs (scattered non-temporal stores
+// would reach HBM as partial lines).
+template <int F>
+__device__ __forceinline__ void store_rec_nt(BinRec<F>* p, const BinRec<F>& r) {
+    constexpr int W = sizeof(BinRec<F>) / 4;  // 32-bit words, a power of two >= 2
+    float w[W];
+    w[0] = __builtin_bit_cast(float, r.slot);
+#pragma unroll
+    for (int j = 0; j < F; ++j) w[1 + j] = r.v[j];
+#pragma unroll
+    for (int j = F + 1; j < W; ++j) w[j] = 0.0f;
+    if constexpr (W == 2) {
+        __builtin_nontemporal_store(f32x2{w[0], w[1]}, reinterpret_cast<f32x2*>(p));
+    } else {
+#pragma unroll
+        for (int c = 0; c < W / 4; ++c)
+            __builtin_nontemporal_store(f32x4{w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]},
+                                        reinterpret_cast<f32x4*>(p) + c);
+    }
+}
+
 // Per-workgroup contiguous range of points.
 __device__ __forceinline__ void bin_chunk(int64_t N, int64_t chunk, int64_t& lo, int64_t& hi) {
     lo = (int64_t)blockIdx.x * chunk;
@@ -193,6 +217,159 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(int64_t N, const
                     recs[pos] = r;
                 }
             });
+        }
+    }
+}
+
+// Staged scatter.  Written straight from the lookup, consecutive lanes send
+// their records to unrelated buckets, so every record is a lone 16-byte store
+// and the L2 fills and writes back partial lines.  Here a workgroup takes
+// its points in rounds of kStageBlock * PPT; per round and level it counts its
+// contributions per bucket in LDS (the atomic's return value is the
+// record's rank within its bucket), scans the counts, places the records in
+// LDS in bucket order, and then writes them out with consecutive threads on
+// consecutive records: each bucket's records of the round form one
+// contiguous run that continues where the workgroup's previous run ended.
+// The records and their positions are the same as the direct kernel's, up to
+// the order within a bucket (which the sums do not depend on beyond
+// rounding).
+constexpr int kStageBlock = 512;  // threads of the staged scatter (longer runs than kStageBlock)
+constexpr int kStageSlots = 12;  // contributions staged per thread per round
+// LDS budget of the staged kernel (one workgroup per CU); configurations
+// that need more use the direct kernel.
+constexpr size_t kStageLdsMax = 150 * 1024;
+
+template <int V>
+constexpr int stage_ppt() { return V > kStageSlots ? 0 : kStageSlots / V; }
+
+// LDS layout of the staged scatter (in 32-bit words): cursors [B], local
+// counts/offsets [bpl + 1], staged keys [CAP], staged values [CAP * F].
+struct StageLds {
+    size_t cursor, loff, key, val, words;
+};
+__host__ __device__ inline size_t stage_round4(size_t w) { return (w + 3) & ~(size_t)3; }
+template <int V, int F>
+__host__ __device__ inline StageLds stage_lds(int B, int bpl) {
+    constexpr size_t CAP = (size_t)kStageBlock * stage_ppt<V>() * V;
+    StageLds s;
+    s.cursor = 0;
+    s.loff = stage_round4((size_t)B);
+    s.key = s.loff + stage_round4((size_t)bpl + 1);
+    s.val = s.key + CAP;
+    s.words = s.val + CAP * F;
+    return s;
+}
+
+template <class Tag, int D, int F, typename GT>
+__global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t N, const float* __restrict__ pts,
+                                                                       const GT* __restrict__ d_out, LevelArgs lv,
+                                                                       BinPlan plan) {
+    constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+    constexpr int PPT = stage_ppt<V>();
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wave_sum[kStageBlock / 64];
+    const StageLds lay = stage_lds<V, F>(plan.B, plan.bpl);
+    uint32_t* cursor = lds + lay.cursor;
+    uint32_t* loff = lds + lay.loff;
+    uint32_t* skey = lds + lay.key;
+    float* sval = reinterpret_cast<float*>(lds + lay.val);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int bpl = plan.bpl;
+
+    const uint32_t* row = plan.counts + (size_t)blockIdx.x * plan.B;
+    for (int b = tid; b < plan.B; b += kStageBlock) cursor[b] = plan.base[b] + row[b];
+    BinRec<F>* __restrict__ recs = reinterpret_cast<BinRec<F>*>(plan.recs);
+    const uint32_t smask = (1u << plan.s_log2) - 1u;
+    int64_t lo, hi;
+    bin_chunk(N, plan.chunk, lo, hi);
+    for (int64_t r0 = lo; r0 < hi; r0 += (int64_t)kStageBlock * PPT) {
+        float y[PPT][D];
+        bool ok[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int64_t pt = r0 + tid + (int64_t)j * kStageBlock;
+            ok[j] = pt < hi;
+            load_point<Tag, D>(pts, ok[j] ? pt : lo, lv.Fn, y[j]);
+        }
+        for (int l = plan.l0; l < plan.l1; ++l) {
+            const uint32_t bl = (uint32_t)(l - plan.l0) * bpl;
+            __syncthreads();  // the previous level's offsets are no longer read
+            for (int b = tid; b <= bpl; b += kStageBlock) loff[b] = 0;
+            __syncthreads();
+            uint32_t key[PPT][V], rank[PPT][V];
+            float val[PPT][V][F];
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) key[j][k] = kNone;
+                if (!ok[j]) continue;
+                const int64_t pt = r0 + tid + (int64_t)j * kStageBlock;
+                float g[F];
+                RowIO<GT, F>::load(d_out + pt * (int64_t)(lv.L * F) + l * F, g);
+                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.mask,
+                               [&](const auto& h, const auto& w, int base, const auto& cell, const auto&) {
+                    constexpr int K = sizeof(w) / sizeof(float);
+                    int32_t e0, stride[D];
+                    if (l < plan.P && dense_cell<D>(plan, l, cell, e0, stride)) return;  // summed in LDS instead
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t b = h[k] >> plan.s_log2;
+                        key[j][base + k] = (h[k] & smask) | (b << 16);
+                        rank[j][base + k] = atomicAdd(&loff[b], 1u);
+#pragma unroll
+                        for (int f = 0; f < F; ++f) val[j][base + k][f] = w[k] * g[f];
+                    }
+                });
+            }
+            __syncthreads();
+            // exclusive scan of the per-bucket counts; loff[bpl] = round total
+            {
+                const int per = (bpl + kStageBlock - 1) / kStageBlock;
+                const int b0 = tid * per < bpl ? tid * per : bpl;
+                const int b1 = b0 + per < bpl ? b0 + per : bpl;
+                uint32_t sum = 0;
+                for (int b = b0; b < b1; ++b) sum += loff[b];
+                uint32_t inc = sum;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t t = __shfl_up(inc, off, 64);
+                    if (lane >= off) inc += t;
+                }
+                if (lane == 63) wave_sum[wave] = inc;
+                __syncthreads();
+                uint32_t run = inc - sum;
+                for (int w = 0; w < wave; ++w) run += wave_sum[w];
+                for (int b = b0; b < b1; ++b) {
+                    const uint32_t c = loff[b];
+                    loff[b] = run;
+                    run += c;
+                }
+                if (tid == kStageBlock - 1) loff[bpl] = run;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PPT; ++j)
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    if (key[j][k] == kNone) continue;
+                    const uint32_t i = loff[key[j][k] >> 16] + rank[j][k];
+                    skey[i] = key[j][k];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) sval[i * F + f] = val[j][k][f];
+                }
+            __syncthreads();
+            const uint32_t total = loff[bpl];
+            for (uint32_t i = tid; i < total; i += kStageBlock) {
+                const uint32_t kk = skey[i], b = kk >> 16;
+                BinRec<F> r;
+                r.slot = kk & smask;
+#pragma unroll
+                for (int f = 0; f < F; ++f) r.v[f] = sval[i * F + f];
+                store_rec_nt<F>(&recs[cursor[bl + b] + (i - loff[b])], r);
+            }
+            __syncthreads();
+            for (int b = tid; b < bpl; b += kStageBlock) cursor[bl + b] += loff[b + 1] - loff[b];
         }
     }
 }
@@ -406,7 +583,18 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     bin_scan_kernel<<<1, 1024, 0, c.stream>>>(p.B, totals, p.base);
     trace_end(c.stream);
     trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + recs);
-    bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv, p);
+    bool staged = false;
+    if constexpr (stage_ppt<V>() >= 1) {
+        const size_t staged_lds = stage_lds<V, F>(p.B, p.bpl).words * sizeof(uint32_t);
+        if (staged_lds <= kStageLdsMax) {
+            bin_scatter_staged_kernel<Tag, D, F, GT><<<p.W, kStageBlock, staged_lds, c.stream>>>(c.N, c.pts, d_out, c.lv,
+                                                                                               p);
+            staged = true;
+        }
+    }
+    if (!staged)
+        bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv,
+                                                                                                p);
     trace_end(c.stream);
     const size_t lds = (size_t)(F << p.s_log2) * sizeof(float);
     if (c.adam.param) {
