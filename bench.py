@@ -34,8 +34,8 @@ COPY_ELEMS = 1 << 26  # calibration copy: 256 MiB read, 128 MiB written
 TRAFFIC_FILE = os.path.join("profiles", "bin_accum_adam_image2d_traffic.json")
 # kernels whose counters the traffic file holds, and the sources that define them
 TRAFFIC_KERNELS = {"bin_accum_adam": ("bin_accum_kernel", "true")}
-TRAFFIC_SOURCES = ["paper_2311_15439_amd/csrc/encode_binned.hpp", "paper_2311_15439_amd/csrc/spx_internal.h",
-                   "paper_2311_15439_amd/csrc/encode_simplex.hip"]
+TRAFFIC_SOURCES = ["paper_2311_15439_amd/csrc/binned_accum.hpp", "paper_2311_15439_amd/csrc/spx_internal.h",
+                   "paper_2311_15439_amd/csrc/encode_kernels.hpp", "paper_2311_15439_amd/csrc/lookup.hpp"]
 
 
 def _sources_digest():

@@ -28,19 +28,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "binned_accum.hpp"
 #include "encode_kernels.hpp"
 
 namespace spx {
 
 constexpr int kBinBlock = 256;
-
-// One record per contribution: slot within the bucket and the F values,
-// padded to a power of two so that a record is one aligned store.
-template <int F>
-struct alignas(F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64) BinRec {
-    uint32_t slot;
-    float v[F];
-};
 
 // Record store that bypasses the caches' write-back: records are read only
 // by the next kernel, and dirty lines left behind in L2 would be written back
@@ -432,129 +425,6 @@ static __global__ __launch_bounds__(kColBuckets * kColSegs) void bin_coarse_redu
     plan.gdense[i] = t;
 }
 
-constexpr int kAccBlock = 512;
-constexpr int kAccUnroll = 4;
-
-// Adam update of four parameters with their summed gradients (the same
-// binary32 operation sequence as the standalone Adam kernel).
-__device__ __forceinline__ void adam4(const AdamArgs& a, f32x4 g, f32x4& p, f32x4& m, f32x4& v, f16x4& h) {
-#pragma clang fp contract(off)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        m[q] = a.b1 * m[q] + (1.0f - a.b1) * g[q];
-        v[q] = a.b2 * v[q] + (1.0f - a.b2) * g[q] * g[q];
-        p[q] = p[q] - a.lr * (m[q] * a.inv_bc1) / (sqrtf(v[q] * a.inv_bc2) + a.eps);
-        h[q] = (f16)p[q];
-    }
-}
-
-constexpr int kAccPre = 8;  // float4 chunks of the slice a thread preloads
-
-template <int D, int F, bool ADAM>
-__global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint32_t T, float* __restrict__ d_tables,
-                                                              AdamArgs adam) {
-    extern __shared__ float acc[];
-    const int S = 1 << plan.s_log2;
-    const int b = blockIdx.x;
-    const int l = plan.l0 + b / plan.bpl;
-    const size_t off = ((size_t)l * T + (size_t)(b % plan.bpl) * S) * F;
-    const int n4 = S * F / 4;
-    const float* base_ptr = ADAM ? adam.param : d_tables;
-    const bool vec = n4 * 4 == S * F && ((uintptr_t)(base_ptr + off) & 15) == 0 && n4 <= kAccPre * kAccBlock;
-    // The slice's state does not depend on the records: issue its loads first
-    // so they overlap the record phase.
-    f32x4 P[kAccPre], M[kAccPre], Vv[kAccPre];
-    if (vec) {
-#pragma unroll
-        for (int c = 0; c < kAccPre; ++c) {
-            const int i = threadIdx.x + c * kAccBlock;
-            if (i < n4) {
-                P[c] = reinterpret_cast<const f32x4*>(base_ptr + off)[i];
-                if constexpr (ADAM) {
-                    M[c] = reinterpret_cast<const f32x4*>(adam.m + off)[i];
-                    Vv[c] = reinterpret_cast<const f32x4*>(adam.v + off)[i];
-                }
-            }
-        }
-    }
-    for (int i = threadIdx.x; i < S * F; i += kAccBlock) acc[i] = 0.0f;
-    __syncthreads();
-    // privatised level: pick up the dense sums whose slot falls in this bucket
-    if (l < plan.P) {
-        const int ext = plan.ext[l];
-        const uint32_t want = (uint32_t)(b % plan.bpl), smask = (uint32_t)S - 1u;
-        for (int e = plan.doff[l] + threadIdx.x; e < plan.doff[l + 1]; e += kAccBlock) {
-            int32_t rem = e - plan.doff[l];
-            uint32_t h = 0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                h ^= (uint32_t)(rem % ext) * hash_prime(i);
-                rem /= ext;
-            }
-            h &= T - 1u;
-            if ((h >> plan.s_log2) != want) continue;
-#pragma unroll
-            for (int j = 0; j < F; ++j) {
-                const float g = plan.gdense[(size_t)e * F + j];
-                if (g != 0.0f) atomicAdd(&acc[(h & smask) * F + j], g);
-            }
-        }
-    }
-    const BinRec<F>* __restrict__ recs = reinterpret_cast<const BinRec<F>*>(plan.recs);
-    const uint32_t r0 = plan.base[b], r1 = plan.base[b + 1];
-    uint32_t r = r0 + threadIdx.x;
-    // several records in flight per thread before their LDS adds
-    for (; r + (kAccUnroll - 1) * kAccBlock < r1; r += kAccUnroll * kAccBlock) {
-        BinRec<F> rec[kAccUnroll];
-#pragma unroll
-        for (int u = 0; u < kAccUnroll; ++u) rec[u] = recs[r + u * kAccBlock];
-#pragma unroll
-        for (int u = 0; u < kAccUnroll; ++u)
-#pragma unroll
-            for (int j = 0; j < F; ++j) atomicAdd(&acc[rec[u].slot * F + j], rec[u].v[j]);
-    }
-    for (; r < r1; r += kAccBlock) {
-        const BinRec<F> rec = recs[r];
-#pragma unroll
-        for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], rec.v[j]);
-    }
-    __syncthreads();
-    if (vec) {
-#pragma unroll
-        for (int c = 0; c < kAccPre; ++c) {
-            const int i = threadIdx.x + c * kAccBlock;
-            if (i >= n4) break;
-            const f32x4 g = reinterpret_cast<const f32x4*>(acc)[i];
-            if constexpr (!ADAM) {
-                reinterpret_cast<f32x4*>(d_tables + off)[i] = P[c] + g;
-            } else {
-                f16x4 h;
-                adam4(adam, g, P[c], M[c], Vv[c], h);
-                reinterpret_cast<f32x4*>(adam.param + off)[i] = P[c];
-                reinterpret_cast<f32x4*>(adam.m + off)[i] = M[c];
-                reinterpret_cast<f32x4*>(adam.v + off)[i] = Vv[c];
-                if (adam.param_f16) reinterpret_cast<f16x4*>((f16*)adam.param_f16 + off)[i] = h;
-            }
-        }
-    } else {
-        for (int i = threadIdx.x; i < S * F; i += kAccBlock) {
-            const float g = acc[i];
-            if constexpr (!ADAM) {
-                d_tables[off + i] += g;
-            } else {
-#pragma clang fp contract(off)
-                const float m = adam.b1 * adam.m[off + i] + (1.0f - adam.b1) * g;
-                const float v = adam.b2 * adam.v[off + i] + (1.0f - adam.b2) * g * g;
-                const float p = adam.param[off + i] - adam.lr * (m * adam.inv_bc1) / (sqrtf(v * adam.inv_bc2) + adam.eps);
-                adam.m[off + i] = m;
-                adam.v[off + i] = v;
-                adam.param[off + i] = p;
-                if (adam.param_f16) ((f16*)adam.param_f16)[off + i] = (f16)p;
-            }
-        }
-    }
-}
-
 template <class Tag, int D, int F, typename GT>
 hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
     const GT* d_out = (const GT*)c.d_out;
@@ -562,7 +432,6 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     const double N = (double)c.N, gs = sizeof(GT), rec = sizeof(BinRec<F>);
     const double counts = (double)p.W * p.B * 4.0;
     const double recs = N * (p.l1 - p.l0 - p.P) * V * rec;  // in-box points emit no records at privatised levels
-    const double slots = (double)p.B * (1 << p.s_log2) * F;
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
     trace_end(c.stream);
@@ -596,16 +465,7 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
         bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv,
                                                                                                 p);
     trace_end(c.stream);
-    const size_t lds = (size_t)(F << p.s_log2) * sizeof(float);
-    if (c.adam.param) {
-        trace_begin(c.stream, "bin_accum_adam", recs + slots * (c.adam.param_f16 ? 26.0 : 24.0));
-        bin_accum_kernel<D, F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, nullptr, c.adam);
-    } else {
-        trace_begin(c.stream, "bin_accum", recs + slots * 8.0);
-        bin_accum_kernel<D, F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, c.d_tables, c.adam);
-    }
-    trace_end(c.stream);
-    return hipGetLastError();
+    return launch_accum<D, F>(c, p, recs);
 }
 
 template <class Tag, int D, int F>
