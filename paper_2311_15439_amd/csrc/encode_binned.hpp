@@ -228,6 +228,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(int64_t N, const
 // rounding).
 constexpr int kStageBlock = 512;  // threads of the staged scatter (longer runs than kStageBlock)
 constexpr int kStageSlots = 12;  // contributions staged per thread per round
+constexpr int kStageGL = 8;      // levels of output gradient held per point
 // LDS budget of the staged kernel (one workgroup per CU); configurations
 // that need more use the direct kernel.
 constexpr size_t kStageLdsMax = 150 * 1024;
@@ -285,7 +286,23 @@ __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t
             ok[j] = pt < hi;
             load_point<Tag, D>(pts, ok[j] ? pt : lo, lv.Fn, y[j]);
         }
+        // The points' output gradients are read kStageGL levels at a time
+        // into registers: between two levels of the same point a whole round
+        // passes, long enough for its row to leave L2, so reading one level
+        // per visit would fetch each row's lines once per level.
+        float gch[PPT][kStageGL][F];
         for (int l = plan.l0; l < plan.l1; ++l) {
+            const int li = (l - plan.l0) % kStageGL;
+            if (li == 0) {
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const int64_t pt = r0 + tid + (int64_t)j * kStageBlock;
+                    const GT* __restrict__ grow = d_out + (ok[j] ? pt : lo) * (int64_t)(lv.L * F);
+#pragma unroll
+                    for (int q = 0; q < kStageGL; ++q)
+                        if (l + q < plan.l1) RowIO<GT, F>::load(grow + (l + q) * F, gch[j][q]);
+                }
+            }
             const uint32_t bl = (uint32_t)(l - plan.l0) * bpl;
             __syncthreads();  // the previous level's offsets are no longer read
             for (int b = tid; b <= bpl; b += kStageBlock) loff[b] = 0;
@@ -297,9 +314,14 @@ __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t
 #pragma unroll
                 for (int k = 0; k < V; ++k) key[j][k] = kNone;
                 if (!ok[j]) continue;
-                const int64_t pt = r0 + tid + (int64_t)j * kStageBlock;
                 float g[F];
-                RowIO<GT, F>::load(d_out + pt * (int64_t)(lv.L * F) + l * F, g);
+#pragma unroll
+                for (int f = 0; f < F; ++f) g[f] = gch[j][0][f];
+#pragma unroll
+                for (int q = 1; q < kStageGL; ++q)
+                    if (li == q)
+#pragma unroll
+                        for (int f = 0; f < F; ++f) g[f] = gch[j][q][f];
                 visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.mask,
                                [&](const auto& h, const auto& w, int base, const auto& cell, const auto&) {
                     constexpr int K = sizeof(w) / sizeof(float);
