@@ -155,6 +155,7 @@ class TrainStep:
         self.ws = torch.empty(spx.spx_mlp_bwd_workspace(self.mlp, self.N), dtype=torch.uint8, device=dev)
         self.bws = torch.empty(spx.spx_encode_bwd_workspace(self.enc, self.N), dtype=torch.uint8, device=dev)
         self.t = 0
+        self.lr = 1e-2
         self.fused = fused
         self.names = ["encode_fwd", "mlp_fwd", "mse_grad", "mlp_bwd",
                       "encode_bwd_adam" if fused else "encode_bwd", "adam_tables", "adam_mlp"]
@@ -175,16 +176,16 @@ class TrainStep:
         rec(4)
         if self.fused:
             # adjoint and Adam on the tables in one pass (no gradient table)
-            spx.spx_encode_bwd_adam(self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=1e-2,
+            spx.spx_encode_bwd_adam(self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr,
                                     beta1=0.9, beta2=0.99, eps=1e-15, step=self.t, workspace=self.bws)
             rec(5)
         else:
             spx.spx_encode_bwd(self.enc, pts, self.dfeats, self.grad, self.bws)
             rec(5)
-            spx.spx_adam_step(self.master, self.grad, self.m, self.v, self.tab16, lr=1e-2, beta1=0.9, beta2=0.99,
+            spx.spx_adam_step(self.master, self.grad, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9, beta2=0.99,
                               eps=1e-15, step=self.t, zero_grad=True)
         rec(6)
-        spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=1e-2, beta1=0.9, beta2=0.99,
+        spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=self.lr, beta1=0.9, beta2=0.99,
                           eps=1e-15, step=self.t, zero_grad=False)
         rec(7)
 
@@ -329,6 +330,18 @@ def time_encode_sweep(reps=30, warm=5):
                 spx.spx_encode_bwd(enc, pts, dout, grad, ws)
                 ev[r][4].record()
             torch.cuda.synchronize()
+            # one traced adjoint: where its time goes, kernel by kernel
+            grad.zero_()
+            trace = spx.Trace(capacity=64)
+            with trace:
+                spx.spx_encode_bwd(enc, pts, dout, grad, ws)
+            bwd_kernels = {}
+            for kname, nbytes, kms in trace.results():
+                k = bwd_kernels.setdefault(kname, {"ms": 0.0, "GB_s": 0.0, "bytes": 0.0})
+                k["ms"] += kms
+                k["bytes"] += nbytes
+            for k in bwd_kernels.values():
+                k["GB_s"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else None
             tw = [e[0].elapsed_time(e[1]) for e in ev]
             f = [e[1].elapsed_time(e[2]) for e in ev]
             z = [e[2].elapsed_time(e[3]) for e in ev]
@@ -338,7 +351,7 @@ def time_encode_sweep(reps=30, warm=5):
             V = enc.n_vertices
             gathers = N * w.n_levels * V
             row[cname] = {"fwd": fq, "zero_grad": _quantiles(z), "bwd": _quantiles(b), "fwd_bwd": tq,
-                          "gather_twin": wq,
+                          "gather_twin": wq, "bwd_kernels": bwd_kernels,
                           "fwd_points_per_s": N / (fq["median_ms"] * 1e-3),
                           "fwd_bwd_points_per_s": N / (tq["median_ms"] * 1e-3),
                           "twin_gathers_per_s": gathers / (wq["median_ms"] * 1e-3),
@@ -356,10 +369,13 @@ def time_encode_sweep(reps=30, warm=5):
 
 
 def equal_accuracy(w, host_tables, weights, d_out, steps=2000, n_train=6):
-    """Accuracy at equal memory: train the image field with the simplex
-    encoding (equal-memory level scaling on) and with the 2^n grid for the
-    same number of steps on the same batches, then compare the PSNR on a
-    held-out batch of pixel positions."""
+    """Accuracy at equal memory: train the field with the simplex encoding
+    (equal-memory level scaling on) and with the 2^n grid for the same number
+    of steps on the same batches, then compare the PSNR on a held-out batch
+    (image: RGB clamped to [0, 1], peak 1; volume: density and colour,
+    peak = the largest held-out target value).  Adam's step size decays
+    from 1e-2 to 1e-3 over the run, so the end point is not dominated by
+    step noise."""
     import torch
     from paper_2311_15439_amd import spx
     batches = []
@@ -368,20 +384,55 @@ def equal_accuracy(w, host_tables, weights, d_out, steps=2000, n_train=6):
         batches.append((p, _targets(w, p, 100 + b)))
     held_p, held_t = batches.pop()
     out = {"steps": steps, "train_batches": n_train, "points_per_step": w.n_points}
-    for cell, em, name in ((spx.SPX_SIMPLEX, True, "simplex_equal_memory"), (spx.SPX_GRID, False, "grid")):
+    for cell, em, name in ((spx.SPX_SIMPLEX, True, "simplex_equal_memory"), (spx.SPX_SIMPLEX, False, "simplex"),
+                           (spx.SPX_GRID, False, "grid")):
         print(f"# equal accuracy: training {name} for {steps} steps", file=sys.stderr, flush=True)
         ts = TrainStep(w, cell, batches, host_tables, weights, d_out, equal_memory=em)
         for i in range(steps):
+            ts.lr = 1e-2 * 0.1 ** (i / steps)  # exponential decay to 1e-3: a settled end point
             ts.step(i)
         hp = torch.from_numpy(held_p).to("cuda")
         ht = torch.from_numpy(held_t).to("cuda")
         spx.spx_encode_fwd(ts.enc, hp, ts.tab16, ts.feats)
         spx.spx_mlp_fwd(ts.mlp, ts.feats, *ts.Wv, ts.y)
-        mse = torch.mean((ts.y.clamp(0, 1) - ht) ** 2).item()
-        out[name] = {"psnr_db": 10.0 * np.log10(1.0 / mse), "mse": mse}
+        if w.name.startswith("image"):
+            mse, peak = torch.mean((ts.y.clamp(0, 1) - ht) ** 2).item(), 1.0
+        else:
+            mse, peak = torch.mean((ts.y - ht) ** 2).item(), float(held_t.max())
+        out[name] = {"psnr_db": 10.0 * np.log10(peak * peak / mse), "mse": mse}
         del ts
         torch.cuda.empty_cache()
     out["simplex_minus_grid_db"] = out["simplex_equal_memory"]["psnr_db"] - out["grid"]["psnr_db"]
+    return out
+
+
+def volume_bench(with_accuracy=True, steps=10, warmup=3):
+    """The volume workload's training step (2^13 rays x 256 samples, n=3,
+    L=16, T=2^19, MLP 32-64-64-4 regressing density and colour), simplex
+    vs the 8-corner grid on the same batches, and their accuracy at equal
+    memory."""
+    import torch
+    from paper_2311_15439_amd import inputs, spx
+    w = inputs.VOLUME_3D
+    print(f"# volume: generating inputs", file=sys.stderr, flush=True)
+    host_tables = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, False)
+    weights = inputs.mlp_weights(w.n_levels * w.n_feat, 64, 4, 9)
+    batches = []
+    for b in range(2):
+        p = _points(w, b)
+        batches.append((p, _targets(w, p, b)))
+    out = {"workload": w.name + f", {w.n_points} points/step, MLP 32-64-64-4"}
+    for cell, name in ((spx.SPX_SIMPLEX, "simplex"), (spx.SPX_GRID, "grid")):
+        print(f"# volume: timing {name} step", file=sys.stderr, flush=True)
+        ts = TrainStep(w, cell, batches, host_tables, weights, 4)
+        ms, per, _, kern = time_steps(ts, steps, warmup)
+        out[name] = {"ms_per_step": ms, "points_per_s": ts.N / (ms * 1e-3),
+                     "kernels_ms": {k: round(v["avg_ms"] * v["launches_per_step"], 5) for k, v in kern.items()}}
+        del ts
+        torch.cuda.empty_cache()
+    out["simplex_speedup"] = out["grid"]["ms_per_step"] / out["simplex"]["ms_per_step"]
+    if with_accuracy:
+        out["equal_accuracy"] = equal_accuracy(w, host_tables, weights, 4, n_train=4)
     return out
 
 
@@ -545,6 +596,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the volume / dimension-sweep encoding timings")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the equal-memory accuracy comparison")
+    ap.add_argument("--no-volume", action="store_true",
+                    help="skip the volume workload's training step (simplex vs grid) and its accuracy comparison")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run two training steps and a binary32->binary16 copy of 2^26 elements, then exit "
                          "(the program profiled by the rocprofv3 --pmc traffic runs)")
@@ -617,8 +670,12 @@ def main():
         torch.cuda.empty_cache()
 
     accuracy = None
-    if not args.no_accuracy and w.name.startswith("image"):
-        accuracy = equal_accuracy(w, host_tables, weights, d_out)
+    if not args.no_accuracy:
+        accuracy = {w.name: equal_accuracy(w, host_tables, weights, d_out)}
+
+    volume = None
+    if not args.no_volume and w.name.startswith("image"):
+        volume = volume_bench(with_accuracy=not args.no_accuracy)
 
     sweep = None
     if not args.no_sweep:
@@ -665,6 +722,7 @@ def main():
         "stream_reference": stream,
         "encode_sweep": sweep,
         "equal_accuracy": accuracy,
+        "volume_step": volume,
         "serving": serving,
         "wall_s_timed": wall,
     }

@@ -282,8 +282,6 @@ spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* 
     if (!workspace || workspace_bytes < lay.total_bytes)
         return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", lay.total_bytes, workspace_bytes);
     if (!aligned(workspace, 256)) return fail(SPX_EALIGN, "workspace not 256-byte aligned");
-    if (lay.groups != 1)
-        return fail(SPX_EUNSUPPORTED, "fused Adam needs all levels in one group (%d groups here)", lay.groups);
     spx::EncodeCall c = base_call(enc, N, pts, stream);
     c.op = spx::EncodeOp::AdjointBinned;
     c.workspace = workspace;

@@ -21,7 +21,7 @@ struct alignas(F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64) BinRec {
 };
 
 constexpr int kAccBlock = 512;
-constexpr int kAccUnroll = 4;
+constexpr int kAccUnroll = 2;
 
 // Adam update of four parameters with their summed gradients (the same
 // binary32 operation sequence as the standalone Adam kernel).
@@ -34,6 +34,48 @@ __device__ __forceinline__ void adam4(const AdamArgs& a, f32x4 g, f32x4& p, f32x
         p[q] = p[q] - a.lr * (m[q] * a.inv_bc1) / (sqrtf(v[q] * a.inv_bc2) + a.eps);
         h[q] = (f16)p[q];
     }
+}
+
+// Adds one record per lane to the LDS accumulator.  A bucket's records are
+// stored in point order, and spatially coherent points (samples along a
+// ray) give runs of records for the same slot; 64 lanes adding to one
+// address serialise in LDS.  So when any lane holds the same slot as the
+// lane before it, the wave first sums each run of equal slots across lanes
+// (a segmented scan) and only the run's last lane adds the sum.  The sums
+// group the same terms in a different order.
+template <int F>
+__device__ __forceinline__ void add_record_wave(float* acc, bool ok, const BinRec<F>& rec) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t key = ok ? rec.slot : 0xFFFFFFFFu;
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool joins = ok && lane > 0 && prev == key;
+    if (__ballot(joins) == 0) {
+        if (ok)
+#pragma unroll
+            for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], rec.v[j]);
+        return;
+    }
+    int start = joins ? 0 : lane;  // first lane of this lane's run
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(start, off, 64);
+        if (lane >= off && t > start) start = t;
+    }
+    float v[F];
+#pragma unroll
+    for (int j = 0; j < F; ++j) v[j] = ok ? rec.v[j] : 0.0f;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const float t = __shfl_up(v[j], off, 64);
+            if (lane - off >= start) v[j] += t;
+        }
+    }
+    const int next_joins = __shfl_down((int)joins, 1, 64);
+    if (ok && (lane == 63 || !next_joins))
+#pragma unroll
+        for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], v[j]);
 }
 
 constexpr int kAccPre = 8;  // float4 chunks of the slice a thread preloads
@@ -90,21 +132,19 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
     }
     const BinRec<F>* __restrict__ recs = reinterpret_cast<const BinRec<F>*>(plan.recs);
     const uint32_t r0 = plan.base[b], r1 = plan.base[b + 1];
-    uint32_t r = r0 + threadIdx.x;
-    // several records in flight per thread before their LDS adds
-    for (; r + (kAccUnroll - 1) * kAccBlock < r1; r += kAccUnroll * kAccBlock) {
+    // several records in flight per thread before their LDS adds; the loop
+    // bounds are uniform over the workgroup (lanes past the end idle)
+    for (uint32_t rb = r0; rb < r1; rb += kAccUnroll * kAccBlock) {
         BinRec<F> rec[kAccUnroll];
+        bool ok[kAccUnroll];
 #pragma unroll
-        for (int u = 0; u < kAccUnroll; ++u) rec[u] = recs[r + u * kAccBlock];
+        for (int u = 0; u < kAccUnroll; ++u) {
+            const uint32_t r = rb + threadIdx.x + u * kAccBlock;
+            ok[u] = r < r1;
+            if (ok[u]) rec[u] = recs[r];
+        }
 #pragma unroll
-        for (int u = 0; u < kAccUnroll; ++u)
-#pragma unroll
-            for (int j = 0; j < F; ++j) atomicAdd(&acc[rec[u].slot * F + j], rec[u].v[j]);
-    }
-    for (; r < r1; r += kAccBlock) {
-        const BinRec<F> rec = recs[r];
-#pragma unroll
-        for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], rec.v[j]);
+        for (int u = 0; u < kAccUnroll; ++u) add_record_wave<F>(acc, ok[u], rec[u]);
     }
     __syncthreads();
     if (vec) {

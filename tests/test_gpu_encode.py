@@ -203,6 +203,37 @@ def test_bwd_parity(case, binned):
     assert np.all(got[cnt == 0] == 0)
 
 
+COHERENT_CASES = [
+    # samples along rays (runs of equal slots at the coarse levels), F = 2
+    ("rays", 3, 2, spx.SPX_SIMPLEX),
+    ("rays", 3, 2, spx.SPX_GRID),
+    # one point repeated: every lane of every wave holds the same slot
+    ("same", 2, 1, spx.SPX_SIMPLEX),
+    ("same", 3, 4, spx.SPX_GRID),
+    ("same", 4, 8, spx.SPX_SIMPLEX),
+]
+
+
+@pytest.mark.parametrize("kind,n,F,cell", COHERENT_CASES)
+def test_binned_bwd_coherent_points(kind, n, F, cell):
+    """The binned adjoint sums runs of records for one slot across lanes
+    before adding them; spatially coherent inputs exercise that path."""
+    res = [4, 16, 60, 200, 700]
+    g, o = _enc_pair(n, res, 14, F, False, cell)
+    if kind == "rays":
+        pts = inputs.ray_points(64, 256, 70 + n)
+    else:
+        pts = np.repeat(inputs.uniform_points(1, n, 71), 5000, axis=0)
+        pts = np.concatenate([pts, inputs.uniform_points(37, n, 72)])
+    d = inputs.gradients(len(pts), len(res) * F, 73)
+    got = _gpu_bwd(g, pts, d, True)
+    ref, mag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
+    tol = (cnt + n + 2) * 2.0 ** -24 * mag + 1e-30
+    err = np.abs(got - ref)
+    assert (err <= tol).all(), f"worst {err.max()} ; {int((err > tol).sum())} slots out of tolerance"
+    assert np.all(got[cnt == 0] == 0)
+
+
 @pytest.mark.parametrize("binned", [False, True], ids=["atomic", "binned"])
 def test_bwd_dot_product_identity(binned):
     """<d, J t> = <J^T d, t> with both sides computed on the GPU."""
@@ -274,16 +305,26 @@ def test_binned_equals_atomic_on_the_image_workload():
     assert np.all(np.abs(a - b) <= 2.0 ** -24 * (w.n_points * 3 + 8) * scale[:, None, :] + 1e-30)
 
 
-@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
-def test_bwd_adam_fused_parity(cell):
+FUSED_CASES = [
+    (3, [4, 16, 64, 200], 13, 20001, spx.SPX_SIMPLEX),
+    (3, [4, 16, 64, 200], 13, 20001, spx.SPX_GRID),
+    # 2^17 points x 64 corners x 16 levels: 134 MB of records per level, so
+    # the binned path runs three level groups (at most 1 GiB of records
+    # each) and applies the Adam step group by group
+    (6, [int(4 * 1.25 ** l) for l in range(16)], 12, (1 << 17) + 3, spx.SPX_GRID),
+]
+
+
+@pytest.mark.parametrize("n,res,log2_T,N,cell", FUSED_CASES)
+def test_bwd_adam_fused_parity(n, res, log2_T, N, cell):
     """Adjoint + Adam in one pass against the oracle's adjoint followed by
     its Adam step.  The GPU's gradient differs from the oracle's by the
     summation bound tolg; that error is carried through the Adam update
     (d m / d g = 1 - b1, d v / d g = 2 (1 - b2) g), on top of the binary32
     roundings of the step itself."""
-    n, res, log2_T, F = 3, [4, 16, 64, 200], 13, 2
+    F = 2
     g, o = _enc_pair(n, res, log2_T, F, True, cell)
-    pts = inputs.uniform_points(20001, n, 31)
+    pts = inputs.uniform_points(N, n, 31)
     d = inputs.gradients(len(pts), len(res) * F, 32) * 1e-3
     shape = g.table_shape
     rng = np.random.default_rng(33)
