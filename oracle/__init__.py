@@ -77,6 +77,8 @@ def lib():
                                      C.c_double, C.c_int64, P]),
             ("orc_cast_f32_f16", None, [C.c_int64, P, P]),
             ("orc_mse_grad", None, [C.c_int64, P, P, C.c_double, P]),
+            ("orc_composite_fwd", None, [C.c_int64, C.c_int, P, P, P]),
+            ("orc_composite_bwd", None, [C.c_int64, C.c_int, P, P, P, P, P]),
         ]:
             fn = getattr(L, name)
             fn.restype = res
@@ -292,3 +294,29 @@ def cast_f32_f16(src) -> np.ndarray:
     out = np.zeros(s.shape, np.uint16)
     lib().orc_cast_f32_f16(s.size, _p(s), _p(out))
     return out
+
+
+# --- volume rendering (Eq. 5) ---------------------------------------------------
+
+def composite_fwd(raw, delta) -> np.ndarray:
+    """raw [R, S, 4] float32 (density, colour before activation), delta
+    [R, S] float32 -> rgba [R, 4] in binary64."""
+    a = np.ascontiguousarray(raw, np.float32)
+    d = np.ascontiguousarray(delta, np.float32)
+    R, S = a.shape[0], a.shape[1]
+    out = np.zeros((R, 4), np.float64)
+    lib().orc_composite_fwd(R, S, _p(a), _p(d), _p(out))
+    return out
+
+
+def composite_bwd(raw, delta, d_rgba, with_mag: bool = False):
+    """Adjoint: d_raw [R, S, 4] (and the magnitude bound terms)."""
+    a = np.ascontiguousarray(raw, np.float32)
+    d = np.ascontiguousarray(delta, np.float32)
+    g = np.ascontiguousarray(d_rgba, np.float64)
+    R, S = a.shape[0], a.shape[1]
+    out = np.zeros((R, S, 4), np.float64)
+    mag = np.zeros((R, S, 4), np.float64) if with_mag else None
+    lib().orc_composite_bwd(R, S, _p(a), _p(d), _p(g), _p(out), _p(mag) if with_mag else None)
+    return (out, mag) if with_mag else out
+

@@ -547,8 +547,8 @@ void orc_mlp_bwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const
 
 /* ------------------------------------------------------------------------ */
 /* Optimizer step for the tables (the paper trains by gradient descent and  */
-/* states no optimizer; Adam, Kingma & Ba 2015, Algorithm 1, is this        */
-/* build's choice).  Binary64 arithmetic on binary32 state; the binary16    */
+/* states no optimizer; Adam, Kingma & Ba 2015, Algorithm 1, is the choice  */
+/* made here).  Binary64 arithmetic on binary32 state; the binary16         */
 /* copy is the round-to-nearest-even image of the updated parameter.        */
 /* step is the 1-based iteration count t.                                  */
 /* ------------------------------------------------------------------------ */
@@ -578,4 +578,90 @@ void orc_mse_grad(int64_t n, const float* y, const float* target, double scale, 
 /* Round-to-nearest-even binary32 -> binary16 copy. */
 void orc_cast_f32_f16(int64_t n, const float* src, uint16_t* dst) {
     for (int64_t i = 0; i < n; ++i) dst[i] = orc_f64_to_f16((double)src[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Volume rendering (Sec. 6, Eq. 5).  The paper states the integral over a   */
+/* ray, C = int T(t) sigma(t) c(t) dt with T(t) = exp(-int sigma); it is     */
+/* evaluated with the usual quadrature over the ray's samples (the radiance  */
+/* field system the paper cites for volume rendering): per sample k,         */
+/*   tau_k = sigma_k * delta_k,  alpha_k = 1 - exp(-tau_k),                  */
+/*   T_k = exp(-(tau_0 + ... + tau_{k-1})),  w_k = T_k * alpha_k,            */
+/*   RGB = sum_k w_k c_k,  A = sum_k w_k  (the ray's opacity).               */
+/* The network's raw outputs map to sigma = softplus(raw_0) and              */
+/* c = sigmoid(raw_1..3) (the paper names no activations; these are a        */
+/* reading).  raw [R*S][4], delta [R*S] (the sample's segment length),       */
+/* out rgba [R][4].  Binary64 throughout.                                    */
+/* ------------------------------------------------------------------------ */
+static double softplus(double x) { return (x > 0.0 ? x : 0.0) + log1p(exp(-fabs(x))); }
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+void orc_composite_fwd(int64_t R, int S, const float* raw, const float* delta, double* rgba) {
+    for (int64_t r = 0; r < R; ++r) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double optical = 0.0; /* tau_0 + ... + tau_{k-1} */
+        for (int k = 0; k < S; ++k) {
+            const float* q = raw + (r * S + k) * 4;
+            const double sigma = softplus(q[0]);
+            const double tau = sigma * (double)delta[r * S + k];
+            const double w = exp(-optical) * (1.0 - exp(-tau));
+            for (int ch = 0; ch < 3; ++ch) acc[ch] += w * sigmoid(q[1 + ch]);
+            acc[3] += w;
+            optical += tau;
+        }
+        for (int ch = 0; ch < 4; ++ch) rgba[r * 4 + ch] = acc[ch];
+    }
+}
+
+/* Adjoint of orc_composite_fwd for d_rgba [R][4]: d_raw [R*S][4].  With
+ * Q = sum_j w_j q_j (q_j = (c_j, 1)), T_{k+1} = T_k exp(-tau_k) and
+ * Q_{<=k} the partial sum up to and including sample k,
+ *   dQ/dtau_k = T_{k+1} q_k - (Q - Q_{<=k}),   dQ/dc_k = w_k,
+ * then through the activations: d sigma/d raw = sigmoid(raw),
+ * d c/d raw = c (1 - c).  mag [R*S][4] (optional) receives the same
+ * expressions with every term replaced by its absolute value. */
+void orc_composite_bwd(int64_t R, int S, const float* raw, const float* delta, const double* d_rgba,
+                       double* d_raw, double* mag) {
+    for (int64_t r = 0; r < R; ++r) {
+        double Q[4] = {0.0, 0.0, 0.0, 0.0};
+        double optical = 0.0;
+        for (int k = 0; k < S; ++k) { /* totals first */
+            const float* q = raw + (r * S + k) * 4;
+            const double tau = softplus(q[0]) * (double)delta[r * S + k];
+            const double w = exp(-optical) * (1.0 - exp(-tau));
+            for (int ch = 0; ch < 3; ++ch) Q[ch] += w * sigmoid(q[1 + ch]);
+            Q[3] += w;
+            optical += tau;
+        }
+        const double* dQ = d_rgba + r * 4;
+        double part[4] = {0.0, 0.0, 0.0, 0.0};
+        optical = 0.0;
+        for (int k = 0; k < S; ++k) {
+            const float* q = raw + (r * S + k) * 4;
+            const double dl = (double)delta[r * S + k];
+            const double tau = softplus(q[0]) * dl;
+            const double Tk = exp(-optical), Tn = exp(-(optical + tau));
+            const double w = Tk * (1.0 - exp(-tau));
+            double c[4];
+            for (int ch = 0; ch < 3; ++ch) c[ch] = sigmoid(q[1 + ch]);
+            c[3] = 1.0;
+            for (int ch = 0; ch < 4; ++ch) part[ch] += w * c[ch];
+            double dtau = 0.0, atau = 0.0;
+            for (int ch = 0; ch < 4; ++ch) {
+                const double rest = Q[ch] - part[ch];
+                dtau += dQ[ch] * (Tn * c[ch] - rest);
+                atau += fabs(dQ[ch]) * (Tn * fabs(c[ch]) + fabs(Q[ch]) + fabs(part[ch]));
+            }
+            const double ds = sigmoid(q[0]) * dl;
+            double* o = d_raw + (r * S + k) * 4;
+            o[0] = dtau * ds;
+            for (int ch = 0; ch < 3; ++ch) o[1 + ch] = dQ[ch] * w * c[ch] * (1.0 - c[ch]);
+            if (mag) {
+                double* m = mag + (r * S + k) * 4;
+                m[0] = atau * ds;
+                for (int ch = 0; ch < 3; ++ch) m[1 + ch] = fabs(dQ[ch]) * w * c[ch] * (1.0 - c[ch]);
+            }
+            optical += tau;
+        }
+    }
 }

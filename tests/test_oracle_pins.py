@@ -530,3 +530,102 @@ def test_mse_grad_matches_autograd():
     ty = torch.tensor(y.astype(np.float64), requires_grad=True)
     torch.nn.functional.mse_loss(ty, torch.tensor(tgt.astype(np.float64))).backward()
     np.testing.assert_allclose(oracle.mse_grad(y, tgt, 2.0 / y.size), ty.grad.numpy(), rtol=1e-15)
+
+
+# ---------------------------------------------------------------- volume rendering (Eq. 5)
+
+def _softplus(x):
+    return np.logaddexp(0.0, np.asarray(x, np.float64))
+
+
+def _sigmoid(x):
+    from scipy.special import expit
+    return expit(np.asarray(x, np.float64))
+
+
+def test_composite_constant_medium_closed_form():
+    """Constant density and colour along the ray: the quadrature telescopes to
+    c (1 - exp(-sigma L)) and opacity 1 - exp(-sigma L), exactly."""
+    rng = np.random.default_rng(40)
+    R, S = 7, 33
+    raw = np.zeros((R, S, 4), np.float32)
+    raw[:, :, :] = rng.normal(size=(R, 1, 4)).astype(np.float32)
+    delta = np.repeat(rng.uniform(0.001, 0.05, (R, 1)), S, axis=1).astype(np.float32)
+    got = oracle.composite_fwd(raw, delta)
+    sigma = _softplus(raw[:, 0, 0])
+    L = delta[:, 0].astype(np.float64) * S
+    a = -np.expm1(-sigma * L)
+    np.testing.assert_allclose(got[:, 3], a, rtol=1e-12)
+    np.testing.assert_allclose(got[:, :3], a[:, None] * _sigmoid(raw[:, 0, 1:]), rtol=1e-12)
+
+
+def test_composite_quadrature_converges_to_the_integral():
+    """Eq. 5 with sigma = a and a colour ramp c(t) = t / L has the integral
+    (1 - e^{-aL}) / (aL) - e^{-aL}; midpoint samples converge to it."""
+    a, L, S = 3.0, 1.0, 8192
+    t = (np.arange(S) + 0.5) / S * L
+    raw = np.zeros((1, S, 4), np.float32)
+    raw[0, :, 0] = np.float32(np.log(np.expm1(a)))  # softplus^-1(a)
+    c = t / L
+    raw[0, :, 1] = np.log(c / (1.0 - c)).astype(np.float32)  # sigmoid^-1(c)
+    delta = np.full((1, S), L / S, np.float32)
+    got = oracle.composite_fwd(raw, delta)[0]
+    exact = (1.0 - math.exp(-a * L)) / (a * L) - math.exp(-a * L)
+    assert abs(got[0] - exact) <= 1e-3 * exact
+    assert abs(got[3] - (1.0 - math.exp(-a * L))) <= 1e-3
+
+
+def test_composite_occlusion_and_empty_space():
+    """An opaque first sample hides everything behind it; empty space adds
+    nothing; a single sample is (1 - e^{-sigma delta}) c."""
+    rng = np.random.default_rng(41)
+    raw = rng.normal(size=(3, 16, 4)).astype(np.float32)
+    raw[0, 0, 0] = 60.0                  # sigma = 60 over delta = 1: alpha = 1 - e^-60
+    raw[1, :, 0] = -40.0                 # sigma ~ 4e-18: empty
+    delta = np.ones((3, 16), np.float32)
+    got = oracle.composite_fwd(raw, delta)
+    np.testing.assert_allclose(got[0, :3], _sigmoid(raw[0, 0, 1:]), rtol=1e-12)
+    assert got[0, 3] == pytest.approx(1.0, abs=1e-15)
+    assert np.all(np.abs(got[1]) < 1e-15)
+    one = oracle.composite_fwd(raw[2:3, :1], delta[2:3, :1])[0]
+    alpha = -np.expm1(-_softplus(raw[2, 0, 0]))
+    np.testing.assert_allclose(one, np.r_[alpha * _sigmoid(raw[2, 0, 1:]), alpha], rtol=1e-12)
+
+
+def test_composite_adjoint_central_differences():
+    """d_raw against central differences of the forward, per entry, on raw
+    values and steps that are exact in binary32 (multiples of 2^-10)."""
+    rng = np.random.default_rng(42)
+    R, S = 3, 12
+    raw = (np.round(rng.normal(size=(R, S, 4)) * 1024) / 1024).astype(np.float32)
+    delta = rng.uniform(0.02, 0.3, (R, S)).astype(np.float32)
+    g = rng.normal(size=(R, 4))
+    ana = oracle.composite_bwd(raw, delta, g)
+    h = 2.0 ** -10
+    num = np.zeros_like(ana)
+    for idx in itertools.product(range(R), range(S), range(4)):
+        up, dn = raw.copy(), raw.copy()
+        up[idx] += np.float32(h)
+        dn[idx] -= np.float32(h)
+        num[idx] = np.sum(g * (oracle.composite_fwd(up, delta) - oracle.composite_fwd(dn, delta))) / (2 * h)
+    np.testing.assert_allclose(ana, num, rtol=2e-5, atol=2e-7)
+
+
+def test_composite_adjoint_matches_autograd():
+    """The same adjoint from float64 autograd of the quadrature."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(43)
+    R, S = 5, 40
+    raw = rng.normal(size=(R, S, 4)).astype(np.float32)
+    delta = rng.uniform(0.01, 0.2, (R, S)).astype(np.float32)
+    g = rng.normal(size=(R, 4))
+    tr = torch.tensor(raw.astype(np.float64), requires_grad=True)
+    sigma = torch.nn.functional.softplus(tr[..., 0])
+    tau = sigma * torch.tensor(delta.astype(np.float64))
+    T = torch.exp(-(torch.cumsum(tau, 1) - tau))
+    w = T * (1.0 - torch.exp(-tau))
+    col = torch.sigmoid(tr[..., 1:])
+    rgba = torch.cat([(w[..., None] * col).sum(1), w.sum(1, keepdim=True)], 1)
+    (rgba * torch.tensor(g)).sum().backward()
+    np.testing.assert_allclose(oracle.composite_fwd(raw, delta), rgba.detach().numpy(), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(oracle.composite_bwd(raw, delta, g), tr.grad.numpy(), rtol=1e-9, atol=1e-13)
