@@ -585,7 +585,8 @@ void orc_cast_f32_f16(int64_t n, const float* src, uint16_t* dst) {
 /* ray, C = int T(t) sigma(t) c(t) dt with T(t) = exp(-int sigma); it is     */
 /* evaluated with the usual quadrature over the ray's samples (the radiance  */
 /* field system the paper cites for volume rendering): per sample k,         */
-/*   tau_k = sigma_k * delta_k,  alpha_k = 1 - exp(-tau_k),                  */
+/*   tau_k = sigma_k * delta_k,  alpha_k = 1 - exp(-tau_k) (evaluated as     */
+/*   -expm1(-tau_k): the same number without cancellation for thin samples), */
 /*   T_k = exp(-(tau_0 + ... + tau_{k-1})),  w_k = T_k * alpha_k,            */
 /*   RGB = sum_k w_k c_k,  A = sum_k w_k  (the ray's opacity).               */
 /* The network's raw outputs map to sigma = softplus(raw_0) and              */
@@ -604,7 +605,7 @@ void orc_composite_fwd(int64_t R, int S, const float* raw, const float* delta, d
             const float* q = raw + (r * S + k) * 4;
             const double sigma = softplus(q[0]);
             const double tau = sigma * (double)delta[r * S + k];
-            const double w = exp(-optical) * (1.0 - exp(-tau));
+            const double w = exp(-optical) * (-expm1(-tau));
             for (int ch = 0; ch < 3; ++ch) acc[ch] += w * sigmoid(q[1 + ch]);
             acc[3] += w;
             optical += tau;
@@ -628,7 +629,7 @@ void orc_composite_bwd(int64_t R, int S, const float* raw, const float* delta, c
         for (int k = 0; k < S; ++k) { /* totals first */
             const float* q = raw + (r * S + k) * 4;
             const double tau = softplus(q[0]) * (double)delta[r * S + k];
-            const double w = exp(-optical) * (1.0 - exp(-tau));
+            const double w = exp(-optical) * (-expm1(-tau));
             for (int ch = 0; ch < 3; ++ch) Q[ch] += w * sigmoid(q[1 + ch]);
             Q[3] += w;
             optical += tau;
@@ -641,7 +642,7 @@ void orc_composite_bwd(int64_t R, int S, const float* raw, const float* delta, c
             const double dl = (double)delta[r * S + k];
             const double tau = softplus(q[0]) * dl;
             const double Tk = exp(-optical), Tn = exp(-(optical + tau));
-            const double w = Tk * (1.0 - exp(-tau));
+            const double w = Tk * (-expm1(-tau));
             double c[4];
             for (int ch = 0; ch < 3; ++ch) c[ch] = sigmoid(q[1 + ch]);
             c[3] = 1.0;

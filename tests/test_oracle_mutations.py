@@ -35,9 +35,9 @@ MUTANTS = {
     "mse sign": ("d_y[i] = scale * ((double)y[i] - (double)target[i]);",
                  "d_y[i] = scale * ((double)target[i] - (double)y[i]);"),
     "adam bias correction": ("double mhat = mi / bc1, vhat = vi / bc2;", "double mhat = mi, vhat = vi / bc2;"),
-    "composite own sample in transmittance": ("const double w = exp(-optical) * (1.0 - exp(-tau));",
-                                              "const double w = exp(-optical - tau) * (1.0 - exp(-tau));"),
-    "composite linear alpha": ("const double w = exp(-optical) * (1.0 - exp(-tau));",
+    "composite own sample in transmittance": ("const double w = exp(-optical) * (-expm1(-tau));",
+                                              "const double w = exp(-optical - tau) * (-expm1(-tau));"),
+    "composite linear alpha": ("const double w = exp(-optical) * (-expm1(-tau));",
                                "const double w = exp(-optical) * tau;"),
     "composite density activation": ("const double sigma = softplus(q[0]);", "const double sigma = exp(q[0]);"),
     "composite adjoint remainder sign": ("dtau += dQ[ch] * (Tn * c[ch] - rest);",
