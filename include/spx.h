@@ -259,6 +259,37 @@ spx_status spx_mse_grad(int64_t n, const float* y, const float* target, float* d
                         hipStream_t stream);
 
 /*
+ * Volume rendering of ray samples (Sec. 6, Eq. 5): the rendering integral
+ * evaluated over each ray's samples with the per-sample quadrature
+ *   sigma_k = softplus(raw_k0), c_k = sigmoid(raw_k1..3),
+ *   alpha_k = 1 - exp(-sigma_k delta_k),
+ *   T_k = exp(-(sigma_0 delta_0 + ... + sigma_{k-1} delta_{k-1})),
+ *   rgba = (sum_k T_k alpha_k c_k, sum_k T_k alpha_k)
+ * (the last component is the ray's opacity; the activations are a reading,
+ * the paper names none).  Binary32 arithmetic.
+ *   n_rays     R >= 0 (0 is a no-op).
+ *   n_samples  S, 1..1024 (SPX_EUNSUPPORTED otherwise), samples of one ray
+ *              in order along the ray.
+ *   raw        device [R*S][4] binary32, 16-byte aligned: the network's raw
+ *              (density, r, g, b) per sample, ray-major.
+ *   delta      device [R*S] binary32, 4-byte aligned: each sample's segment
+ *              length along its ray.
+ *   rgba       device [R][4] binary32, 16-byte aligned, overwritten.
+ */
+spx_status spx_composite_fwd(int64_t n_rays, int32_t n_samples, const float* raw, const float* delta, float* rgba,
+                             hipStream_t stream);
+
+/*
+ * Adjoint of spx_composite_fwd: given d_rgba (device [R][4] binary32,
+ * 16-byte aligned), writes d_raw (device [R*S][4] binary32, 16-byte
+ * aligned, overwritten) = d rgba / d raw contracted with d_rgba.  The
+ * forward quantities are recomputed from raw and delta (nothing is saved
+ * between the calls).  Same argument rules as the forward.
+ */
+spx_status spx_composite_bwd(int64_t n_rays, int32_t n_samples, const float* raw, const float* delta,
+                             const float* d_rgba, float* d_raw, hipStream_t stream);
+
+/*
  * Tiny fully connected network of Sec. 5 step (e): d_in -> hidden -> hidden
  * -> d_out, ReLU after the two hidden layers, linear output.
  *   d_in    32 (the concatenated features, L*F; other widths return

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libspx.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPX_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "encode_simplex.hip", "encode_grid.hip", "mlp.hip", "optim.hip", "field_query.hip"]
+SOURCES = ["api.hip", "encode_simplex.hip", "encode_grid.hip", "mlp.hip", "optim.hip", "field_query.hip",
+           "composite.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -314,6 +314,29 @@ spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts
     return from_hip(run(enc, c), "spx_encode_debug launch");
 }
 
+spx_status spx_composite_fwd(int64_t n_rays, int32_t n_samples, const float* raw, const float* delta, float* rgba,
+                             hipStream_t stream) {
+    if (n_rays < 0) return fail(SPX_EINVAL, "n_rays < 0");
+    if (n_samples < 1 || n_samples > 1024) return fail(SPX_EUNSUPPORTED, "n_samples=%d outside 1..1024", n_samples);
+    if (n_rays == 0) return SPX_OK;
+    if (!raw || !delta || !rgba) return fail(SPX_EINVAL, "raw, delta or rgba is NULL");
+    if (!aligned(raw, 16) || !aligned(delta, 4) || !aligned(rgba, 16))
+        return fail(SPX_EALIGN, "raw/rgba must be 16-byte and delta 4-byte aligned");
+    return from_hip(spx::composite_fwd(n_rays, n_samples, raw, delta, rgba, stream), "spx_composite_fwd launch");
+}
+
+spx_status spx_composite_bwd(int64_t n_rays, int32_t n_samples, const float* raw, const float* delta,
+                             const float* d_rgba, float* d_raw, hipStream_t stream) {
+    if (n_rays < 0) return fail(SPX_EINVAL, "n_rays < 0");
+    if (n_samples < 1 || n_samples > 1024) return fail(SPX_EUNSUPPORTED, "n_samples=%d outside 1..1024", n_samples);
+    if (n_rays == 0) return SPX_OK;
+    if (!raw || !delta || !d_rgba || !d_raw) return fail(SPX_EINVAL, "raw, delta, d_rgba or d_raw is NULL");
+    if (!aligned(raw, 16) || !aligned(delta, 4) || !aligned(d_rgba, 16) || !aligned(d_raw, 16))
+        return fail(SPX_EALIGN, "raw/d_rgba/d_raw must be 16-byte and delta 4-byte aligned");
+    return from_hip(spx::composite_bwd(n_rays, n_samples, raw, delta, d_rgba, d_raw, stream),
+                    "spx_composite_bwd launch");
+}
+
 spx_status spx_cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t stream) {
     if (n < 0) return fail(SPX_EINVAL, "n < 0");
     if (n == 0) return SPX_OK;

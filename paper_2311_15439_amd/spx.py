@@ -72,6 +72,8 @@ _SIGNATURES = {
                                       C.c_float, C.c_float, C.c_int64, _P, C.c_size_t, _P]),
     "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_encode_gather_twin": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
+    "spx_composite_fwd": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P]),
+    "spx_composite_bwd": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P, _P]),
     "spx_cast_f32_f16": (C.c_int, [C.c_int64, _P, _P, _P]),
     "spx_adam_step": (C.c_int, [C.c_int64, _P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
                                 C.c_float, C.c_int64, C.c_int32, _P]),
@@ -303,6 +305,31 @@ def spx_encode_gather_twin(enc: Encoding, pts, tables, out, stream=None) -> None
     _check(lib().spx_encode_gather_twin(enc.ref(), N, _dev(pts, torch.float32, "pts"),
                                         _dev(tables, torch.float16, "tables"), _dev(out, torch.float16, "out"),
                                         _stream(stream)), "spx_encode_gather_twin")
+
+
+def spx_composite_fwd(raw, delta, rgba, stream=None) -> None:
+    """raw [R, S, 4] float32, delta [R, S] float32 -> rgba [R, 4] float32."""
+    torch = _torch()
+    if raw.dim() != 3 or raw.shape[2] != 4 or tuple(delta.shape) != tuple(raw.shape[:2]):
+        raise ValueError("raw must be [R, S, 4] and delta [R, S]")
+    if tuple(rgba.shape) != (raw.shape[0], 4):
+        raise ValueError("rgba must be [R, 4]")
+    f = torch.float32
+    _check(lib().spx_composite_fwd(raw.shape[0], raw.shape[1], _dev(raw, f, "raw"), _dev(delta, f, "delta"),
+                                   _dev(rgba, f, "rgba"), _stream(stream)), "spx_composite_fwd")
+
+
+def spx_composite_bwd(raw, delta, d_rgba, d_raw, stream=None) -> None:
+    """d_raw [R, S, 4] = adjoint of spx_composite_fwd applied to d_rgba [R, 4]."""
+    torch = _torch()
+    if raw.dim() != 3 or raw.shape[2] != 4 or tuple(delta.shape) != tuple(raw.shape[:2]):
+        raise ValueError("raw must be [R, S, 4] and delta [R, S]")
+    if tuple(d_rgba.shape) != (raw.shape[0], 4) or tuple(d_raw.shape) != tuple(raw.shape):
+        raise ValueError("d_rgba must be [R, 4] and d_raw like raw")
+    f = torch.float32
+    _check(lib().spx_composite_bwd(raw.shape[0], raw.shape[1], _dev(raw, f, "raw"), _dev(delta, f, "delta"),
+                                   _dev(d_rgba, f, "d_rgba"), _dev(d_raw, f, "d_raw"), _stream(stream)),
+           "spx_composite_bwd")
 
 
 # --------------------------------------------------------------- elementwise
