@@ -214,6 +214,113 @@ class TrainStep:
         }
 
 
+class RenderStep(TrainStep):
+    """Volume-rendering training step: the rays' samples are encoded, the
+    network gives (density, colour) per sample, the samples are composited
+    along each ray (Eq. 5 quadrature) and the loss is on the rays' colours
+    and opacities; its gradient flows back through the compositing, the
+    network and the encoding."""
+
+    def __init__(self, w, cell, batches, host_tables, weights, n_samples, equal_memory=False):
+        # batches: (points [R*S, 3], delta [R*S], target rgba [R, 4])
+        import torch
+        super().__init__(w, cell, [(p, t) for p, _, t in batches], host_tables, weights, 4,
+                         equal_memory=equal_memory)
+        self.S = n_samples
+        self.R = self.N // n_samples
+        self.deltas = [torch.from_numpy(d.reshape(self.R, self.S)).to("cuda") for _, d, _ in batches]
+        self.rgba = torch.empty((self.R, 4), dtype=torch.float32, device="cuda")
+        self.drgba = torch.empty_like(self.rgba)
+        self.names = ["encode_fwd", "mlp_fwd", "composite_fwd", "mse_grad", "composite_bwd", "mlp_bwd",
+                      "encode_bwd_adam", "adam_mlp"]
+
+    def step(self, b, ev=None):
+        spx = self.spx
+        pts, tgt = self.batches[b % len(self.batches)]
+        delta = self.deltas[b % len(self.deltas)]
+        self.t += 1
+        rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+        raw = self.y.view(self.R, self.S, 4)
+        rec(0)
+        spx.spx_encode_fwd(self.enc, pts, self.tab16, self.feats)
+        rec(1)
+        spx.spx_mlp_fwd(self.mlp, self.feats, *self.Wv, self.y)
+        rec(2)
+        spx.spx_composite_fwd(raw, delta, self.rgba)
+        rec(3)
+        spx.spx_mse_grad(self.rgba, tgt, self.drgba, 2.0 / (self.R * 4))
+        rec(4)
+        spx.spx_composite_bwd(raw, delta, self.drgba, self.dy.view(self.R, self.S, 4))
+        rec(5)
+        spx.spx_mlp_bwd(self.mlp, self.feats, *self.Wv, self.dy, self.dfeats, *self.dWv, self.ws)
+        rec(6)
+        spx.spx_encode_bwd_adam(self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr,
+                                beta1=0.9, beta2=0.99, eps=1e-15, step=self.t, workspace=self.bws)
+        rec(7)
+        spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=self.lr, beta1=0.9, beta2=0.99,
+                          eps=1e-15, step=self.t, zero_grad=False)
+        rec(8)
+
+
+def _render_batch(w, b, n_samples):
+    """Ray samples, their segment lengths, and the target colour and opacity
+    of each ray: the procedural density field rendered along the same rays
+    (its density and colour mapped through the inverse activations and
+    composited by the library, once, at set-up)."""
+    import torch
+    from paper_2311_15439_amd import inputs, spx
+    R = w.n_points // n_samples
+    p = inputs.ray_points(R, n_samples, w.seed_points + 1000 * b)
+    pr = p.reshape(R, n_samples, 3).astype(np.float64)
+    seg = np.linalg.norm(np.diff(pr, axis=1), axis=2)
+    delta = np.concatenate([seg, seg[:, -1:]], axis=1).astype(np.float32)
+    field = inputs.procedural_density(p, 7).reshape(R, n_samples, 4).astype(np.float64)
+    raw = np.empty_like(field)
+    raw[..., 0] = np.log(np.expm1(np.maximum(field[..., 0], 1e-6)))       # softplus^-1
+    c = np.clip(field[..., 1:], 1e-4, 1 - 1e-4)
+    raw[..., 1:] = np.log(c / (1.0 - c))                                   # sigmoid^-1
+    traw = torch.from_numpy(raw.astype(np.float32)).cuda()
+    rgba = torch.empty((R, 4), dtype=torch.float32, device="cuda")
+    spx.spx_composite_fwd(traw, torch.from_numpy(delta).cuda(), rgba)
+    return p, delta.reshape(-1), rgba.cpu().numpy()
+
+
+def render_bench(steps=10, warmup=3, train_steps=1000):
+    """The volume workload as a rendering task (NeRF-style): training step
+    simplex vs grid, and held-out PSNR of the rendered rays after
+    train_steps steps (step size decaying 1e-2 -> 1e-3)."""
+    import torch
+    from paper_2311_15439_amd import inputs, spx
+    w = inputs.VOLUME_3D
+    S = 256
+    print("# rendering: generating rays and targets", file=sys.stderr, flush=True)
+    host_tables = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, False)
+    weights = inputs.mlp_weights(w.n_levels * w.n_feat, 64, 4, 9)
+    batches = [_render_batch(w, b, S) for b in range(3)]
+    held = batches.pop()
+    out = {"workload": f"{w.name}, {w.n_points // S} rays x {S} samples per step, MLP 32-64-64-4, "
+                       "loss on composited ray colour and opacity"}
+    for cell, name in ((spx.SPX_SIMPLEX, "simplex"), (spx.SPX_GRID, "grid")):
+        print(f"# rendering: {name} step", file=sys.stderr, flush=True)
+        rs = RenderStep(w, cell, batches, host_tables, weights, S)
+        ms, per, _, kern = time_steps(rs, steps, warmup)
+        for i in range(train_steps):
+            rs.lr = 1e-2 * 0.1 ** (i / train_steps)
+            rs.step(i)
+        hp = torch.from_numpy(held[0]).cuda()
+        spx.spx_encode_fwd(rs.enc, hp, rs.tab16, rs.feats)
+        spx.spx_mlp_fwd(rs.mlp, rs.feats, *rs.Wv, rs.y)
+        spx.spx_composite_fwd(rs.y.view(rs.R, S, 4), torch.from_numpy(held[1].reshape(rs.R, S)).cuda(), rs.rgba)
+        mse = torch.mean((rs.rgba - torch.from_numpy(held[2]).cuda()) ** 2).item()
+        out[name] = {"ms_per_step": ms, "samples_per_s": rs.N / (ms * 1e-3), "rays_per_s": rs.R / (ms * 1e-3),
+                     "kernels_ms": {k: round(v["avg_ms"] * v["launches_per_step"], 5) for k, v in kern.items()},
+                     "heldout_psnr_db": 10.0 * np.log10(1.0 / mse), "train_steps": train_steps}
+        del rs
+        torch.cuda.empty_cache()
+    out["simplex_speedup"] = out["grid"]["ms_per_step"] / out["simplex"]["ms_per_step"]
+    return out
+
+
 def time_steps(ts, steps, warmup):
     """Whole-step time (events around the K steps) plus, from the library's
     kernel trace of the same steps, every kernel's average duration and its
@@ -598,6 +705,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the equal-memory accuracy comparison")
     ap.add_argument("--no-volume", action="store_true",
                     help="skip the volume workload's training step (simplex vs grid) and its accuracy comparison")
+    ap.add_argument("--no-render", action="store_true",
+                    help="skip the volume-rendering training step (compositing along rays), simplex vs grid")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run two training steps and a binary32->binary16 copy of 2^26 elements, then exit "
                          "(the program profiled by the rocprofv3 --pmc traffic runs)")
@@ -677,6 +786,10 @@ def main():
     if not args.no_volume and w.name.startswith("image"):
         volume = volume_bench(with_accuracy=not args.no_accuracy)
 
+    render = None
+    if not args.no_render and w.name.startswith("image"):
+        render = render_bench()
+
     sweep = None
     if not args.no_sweep:
         sweep = time_encode_sweep()
@@ -723,6 +836,7 @@ def main():
         "encode_sweep": sweep,
         "equal_accuracy": accuracy,
         "volume_step": volume,
+        "render_step": render,
         "serving": serving,
         "wall_s_timed": wall,
     }
