@@ -77,6 +77,7 @@ def lib():
                                      C.c_double, C.c_int64, P]),
             ("orc_cast_f32_f16", None, [C.c_int64, P, P]),
             ("orc_mse_grad", None, [C.c_int64, P, P, C.c_double, P]),
+            ("orc_encode_input_grad", None, [P, C.c_int64, P, P, P, P, P]),
             ("orc_composite_fwd", None, [C.c_int64, C.c_int, P, P, P]),
             ("orc_composite_bwd", None, [C.c_int64, C.c_int, P, P, P, P, P]),
         ]:
@@ -294,6 +295,18 @@ def cast_f32_f16(src) -> np.ndarray:
     out = np.zeros(s.shape, np.uint16)
     lib().orc_cast_f32_f16(s.size, _p(s), _p(out))
     return out
+
+
+def encode_input_grad(e: Encoding, pts, tables, d_out, with_mag: bool = False):
+    """d L / d x [N, n] in binary64 for the output gradient d_out [N, L*F]."""
+    x = _pts(pts, e.n_dims)
+    t = _tables(e, tables)
+    g = np.ascontiguousarray(d_out, np.float64)
+    out = np.zeros((len(x), e.n_dims), np.float64)
+    mag = np.zeros_like(out) if with_mag else None
+    ce = e._c()
+    lib().orc_encode_input_grad(C.byref(ce), len(x), _p(x), _p(t), _p(g), _p(out), _p(mag) if with_mag else None)
+    return (out, mag) if with_mag else out
 
 
 # --- volume rendering (Eq. 5) ---------------------------------------------------

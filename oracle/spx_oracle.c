@@ -429,6 +429,89 @@ void orc_encode_bwd(const orc_encoding* e, int64_t N, const float* pts, const do
     }
 }
 
+/*
+ * Gradient with respect to the input point (the derivative the paper's
+ * backward pass leaves out; needed when the encoded coordinates are
+ * themselves optimised).  Inside a simplex the weights are affine in the
+ * fractional parts: f of the k-th sorted axis enters w_k with a minus sign
+ * and w_{k+1} with a plus sign (Sec. 4.3), so the output's derivative along
+ * that axis is t(v_{k+1}) - t(v_k), the difference across the walk's k-th
+ * step.  For the grid, d w_b / d f_i = (b_i ? 1 : -1) prod_{j != i}
+ * (b_j ? f_j : 1 - f_j).  The fractional parts move with p = sigma * y, and
+ * y = x + F_n (sum x) 1 (Eq. 2) for the simplex (p = sigma * x for the
+ * grid), so d p_i / d x_m = sigma (delta_im + F_n) resp. sigma delta_im.
+ * On a face the one-sided derivative of the simplex the tie rule picks is
+ * returned.  d_out: [N, L*F] binary64; d_pts [N, n] binary64 (overwritten);
+ * mag (optional) [N, n]: the same sums over absolute values of the terms.
+ */
+void orc_encode_input_grad(const orc_encoding* e, int64_t N, const float* pts, const void* tables,
+                           const double* d_out, double* d_pts, double* mag) {
+    int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
+    size_t T = (size_t)1 << e->log2_T;
+    float sigma[ORC_MAX_LEVELS];
+    orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
+    const double Fn = orc_skew_factor(n);
+#pragma omp parallel for schedule(static)
+    for (int64_t pt = 0; pt < N; ++pt) {
+        const float* x = pts + pt * n;
+        float y[ORC_MAX_DIM];
+        skew_point_f32(n, x, y);
+        double dx[ORC_MAX_DIM] = {0}, ax[ORC_MAX_DIM] = {0};
+        for (int l = 0; l < L; ++l) {
+            int32_t verts[1 << ORC_MAX_DIM][ORC_MAX_DIM];
+            double w64[1 << ORC_MAX_DIM];
+            float w32[1 << ORC_MAX_DIM], p[ORC_MAX_DIM];
+            lookup(e, x, y, sigma[l], verts, w64, w32, p);
+            double g[ORC_MAX_DIM] = {0}, a[ORC_MAX_DIM] = {0}; /* d L / d f_i and its magnitude */
+            double t[1 << ORC_MAX_DIM][8];
+            for (int k = 0; k < V; ++k) {
+                uint32_t h = orc_hash(verts[k], n, e->log2_T);
+                for (int j = 0; j < F; ++j) t[k][j] = table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j);
+            }
+            const double* d = d_out + (size_t)pt * L * F + (size_t)l * F;
+            if (e->cell == ORC_GRID) {
+                double f[ORC_MAX_DIM];
+                for (int i = 0; i < n; ++i) f[i] = (double)p[i] - floor((double)p[i]);
+                for (int b = 0; b < V; ++b)
+                    for (int i = 0; i < n; ++i) {
+                        double c = ((b >> i) & 1) ? 1.0 : -1.0;
+                        for (int m = 0; m < n; ++m)
+                            if (m != i) c *= ((b >> m) & 1) ? f[m] : 1.0 - f[m];
+                        for (int j = 0; j < F; ++j) {
+                            g[i] += c * t[b][j] * d[j];
+                            a[i] += fabs(c * t[b][j] * d[j]);
+                        }
+                    }
+            } else {
+                for (int k = 0; k < n; ++k) {
+                    int axis = 0; /* the axis stepped from vertex k to vertex k+1 */
+                    for (int i = 0; i < n; ++i)
+                        if (verts[k + 1][i] != verts[k][i]) axis = i;
+                    for (int j = 0; j < F; ++j) {
+                        g[axis] += (t[k + 1][j] - t[k][j]) * d[j];
+                        a[axis] += (fabs(t[k + 1][j]) + fabs(t[k][j])) * fabs(d[j]);
+                    }
+                }
+            }
+            double gs = 0.0, as = 0.0;
+            for (int i = 0; i < n; ++i) { gs += g[i]; as += a[i]; }
+            for (int m = 0; m < n; ++m) {
+                if (e->cell == ORC_GRID) {
+                    dx[m] += (double)sigma[l] * g[m];
+                    ax[m] += (double)sigma[l] * a[m];
+                } else {
+                    dx[m] += (double)sigma[l] * (g[m] + Fn * gs);
+                    ax[m] += (double)sigma[l] * (a[m] + Fn * as);
+                }
+            }
+        }
+        for (int m = 0; m < n; ++m) {
+            d_pts[pt * n + m] = dx[m];
+            if (mag) mag[pt * n + m] = ax[m];
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Tiny fully connected network (Sec. 5 step (e); about 7k parameters):     */
 /* in -> H -> H -> out with ReLU on the hidden layers and a linear output.  */

@@ -35,6 +35,9 @@ MUTANTS = {
     "mse sign": ("d_y[i] = scale * ((double)y[i] - (double)target[i]);",
                  "d_y[i] = scale * ((double)target[i] - (double)y[i]);"),
     "adam bias correction": ("double mhat = mi / bc1, vhat = vi / bc2;", "double mhat = mi, vhat = vi / bc2;"),
+    "input grad skew chain": ("dx[m] += (double)sigma[l] * (g[m] + Fn * gs);", "dx[m] += (double)sigma[l] * g[m];"),
+    "input grad walk difference": ("g[axis] += (t[k + 1][j] - t[k][j]) * d[j];", "g[axis] += (t[k][j] - t[k + 1][j]) * d[j];"),
+    "input grad grid sign": ("double c = ((b >> i) & 1) ? 1.0 : -1.0;", "double c = 1.0;"),
     "composite own sample in transmittance": ("const double w = exp(-optical) * (-expm1(-tau));",
                                               "const double w = exp(-optical - tau) * (-expm1(-tau));"),
     "composite linear alpha": ("const double w = exp(-optical) * (-expm1(-tau));",

@@ -629,3 +629,65 @@ def test_composite_adjoint_matches_autograd():
     (rgba * torch.tensor(g)).sum().backward()
     np.testing.assert_allclose(oracle.composite_fwd(raw, delta), rgba.detach().numpy(), rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(oracle.composite_bwd(raw, delta, g), tr.grad.numpy(), rtol=1e-9, atol=1e-13)
+
+
+# ---------------------------------------------------------------- input gradient
+
+@pytest.mark.parametrize("n,res,log2_T,cell", [(2, [7, 23], 14, oracle.SIMPLEX), (3, [3, 5], 20, oracle.SIMPLEX),
+                                                (4, [3], 20, oracle.SIMPLEX), (2, [7, 23], 14, oracle.GRID),
+                                                (3, [3, 5], 20, oracle.GRID)])
+def test_input_grad_of_affine_tables(n, res, log2_T, cell):
+    """Tables holding an affine function A v + b of the lattice point give
+    out = A p + b with p = sigma * skew(x) (Eq. 2; sigma * x for the grid),
+    so d out / d x = sigma A (I + F_n 1 1^T) (resp. sigma A) everywhere."""
+    F = 2
+    boxes = _injective_box(n, res, log2_T)
+    rng = np.random.default_rng(15)
+    A = np.round(rng.uniform(-1, 1, (F, n)) * 4)
+    b = np.round(rng.uniform(-1, 1, F) * 4)
+    tab = np.zeros((len(res), 1 << log2_T, F), np.float32)
+    for l, (verts, slots) in enumerate(boxes):
+        tab[l, slots] = (verts @ A.T + b).astype(np.float32)
+    e = oracle.Encoding(n, res, log2_T, n_feat=F, cell=cell)
+    x = inputs.uniform_points(500, n, 16)
+    sig = oracle.level_scales(n, res, cell=cell).astype(np.float64)
+    Fn = (math.sqrt(n + 1) - 1) / n if cell == oracle.SIMPLEX else 0.0
+    J = np.eye(n) + Fn * np.ones((n, n))
+    for l in range(len(res)):
+        for j in range(F):
+            d = np.zeros((len(x), len(res) * F))
+            d[:, l * F + j] = 1.0
+            got = oracle.encode_input_grad(e, x, tab, d)
+            expect = sig[l] * (A[j] @ J)
+            np.testing.assert_allclose(got, np.broadcast_to(expect, got.shape), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("cell", [oracle.SIMPLEX, oracle.GRID])
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_input_grad_central_differences(n, cell):
+    """Against central differences of the forward on generic tables, where
+    the two one-sided differences agree (no face crossed at any level).  The
+    step is 2^-12: the binary32 skew rounds y to about 2^-24 |y|, which
+    limits the differences to about 2^-11 relative accuracy."""
+    res = [4, 11, 30]
+    e = oracle.Encoding(n, res, 12, n_feat=2, cell=cell)
+    tab = inputs.tables(len(res), 1 << 12, 2, 1.0, 17 + n, False)
+    x = (np.round(inputs.uniform_points(300, n, 18 + n).astype(np.float64) * 2 ** 16) / 2 ** 16).astype(np.float32)
+    d = inputs.gradients(len(x), len(res) * 2, 19 + n).astype(np.float64)
+    ana = oracle.encode_input_grad(e, x, tab, d)
+    h = 2.0 ** -12
+    checked = 0
+    for m in range(n):
+        up, dn = x.copy(), x.copy()
+        up[:, m] += np.float32(h)
+        dn[:, m] -= np.float32(h)
+        f0 = (oracle.encode_fwd(e, x, tab) * d).sum(1)
+        fu = (oracle.encode_fwd(e, up, tab) * d).sum(1)
+        fd = (oracle.encode_fwd(e, dn, tab) * d).sum(1)
+        right, left = (fu - f0) / h, (f0 - fd) / h
+        scale = np.abs(ana[:, m]).max()
+        smooth = np.abs(right - left) <= 4e-3 * scale
+        assert smooth.mean() > 0.7
+        np.testing.assert_allclose(ana[smooth, m], ((fu - fd) / (2 * h))[smooth], rtol=0, atol=2e-3 * scale)
+        checked += smooth.sum()
+    assert checked > 0
