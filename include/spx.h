@@ -213,6 +213,22 @@ spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts
                             float* w, hipStream_t stream);
 
 /*
+ * Gradient of the encoding with respect to the input points, contracted
+ * with the output gradient: d_pts[i] = sum over levels and features of
+ * d_out * d out / d x_i.  Inside a simplex the weights are affine in the
+ * fractional parts (Sec. 4.3): the derivative along the axis of the walk's
+ * k-th step is the difference of the rows of vertices k+1 and k; it is
+ * chained through p = sigma_l * skew(x) (Eq. 2).  The grid cell
+ * differentiates its n-linear weights.  On a face, the one-sided derivative
+ * of the simplex (or cell) the lookup picks is returned.
+ *   tables  as spx_encode_fwd.
+ *   d_out   device [N][L*F] binary32 or binary16 (d_out_dtype), row-aligned.
+ *   d_pts   device [N][n] binary32, 4-byte aligned, overwritten.
+ */
+spx_status spx_encode_input_grad(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
+                                 const void* d_out, int32_t d_out_dtype, float* d_pts, hipStream_t stream);
+
+/*
  * Gather twin: a measurement reference for the forward, not part of the
  * method.  It streams the same points, finds the same cell at every level
  * and gathers the same number of table rows with the same per-level

@@ -202,6 +202,27 @@ spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, 
     return from_hip(run(enc, c), "spx_encode_fwd launch");
 }
 
+spx_status spx_encode_input_grad(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
+                                 const void* d_out, int32_t d_out_dtype, float* d_pts, hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (d_out_dtype != SPX_F32 && d_out_dtype != SPX_F16) return fail(SPX_EINVAL, "d_out_dtype=%d", d_out_dtype);
+    if (N == 0) return SPX_OK;
+    if (!tables || !d_out || !d_pts) return fail(SPX_EINVAL, "tables, d_out or d_pts is NULL");
+    const int te = enc->table_dtype == SPX_F16 ? 2 : 4, ge = d_out_dtype == SPX_F16 ? 2 : 4;
+    if (!aligned(tables, row_align(enc->n_feat, te))) return fail(SPX_EALIGN, "tables not row-aligned");
+    if (!aligned(d_out, row_align(enc->n_feat, ge))) return fail(SPX_EALIGN, "d_out not row-aligned");
+    if (!aligned(d_pts, 4)) return fail(SPX_EALIGN, "d_pts not 4-byte aligned");
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::InputGrad;
+    c.tables = tables;
+    c.d_out = d_out;
+    c.dout_f16 = d_out_dtype == SPX_F16;
+    c.out = d_pts;
+    return from_hip(run(enc, c), "spx_encode_input_grad launch");
+}
+
 spx_status spx_encode_gather_twin(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
                                   void* out, hipStream_t stream) {
     spx_status st = check_encoding(enc);

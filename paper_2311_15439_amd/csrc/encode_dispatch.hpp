@@ -48,6 +48,24 @@ hipError_t bwd_dispatch_types(const EncodeCall& c) {
     return hipGetLastError();
 }
 
+template <class Tag, int D, int F>
+hipError_t input_grad_dispatch_types(const EncodeCall& c) {
+    dim3 g(grid_for(c.N)), b(kBlock);
+    const double per_pt = 8.0 * D + (double)c.lv.L * F * ((c.dout_f16 ? 2 : 4) + vertices<Tag, D>() * (c.table_f16 ? 2 : 4));
+    trace_begin(c.stream, "encode_input_grad", per_pt * (double)c.N);
+    float* o = (float*)c.out;
+    if (c.table_f16 && c.dout_f16)
+        encode_input_grad_kernel<Tag, D, F, f16, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (const f16*)c.d_out, o, c.lv);
+    else if (c.table_f16)
+        encode_input_grad_kernel<Tag, D, F, f16, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (const float*)c.d_out, o, c.lv);
+    else if (c.dout_f16)
+        encode_input_grad_kernel<Tag, D, F, float, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (const f16*)c.d_out, o, c.lv);
+    else
+        encode_input_grad_kernel<Tag, D, F, float, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (const float*)c.d_out, o, c.lv);
+    trace_end(c.stream);
+    return hipGetLastError();
+}
+
 template <class Tag, int D>
 hipError_t dispatch_F(const EncodeCall& c) {
     if (c.op == EncodeOp::AdjointBinned) {
@@ -56,6 +74,15 @@ hipError_t dispatch_F(const EncodeCall& c) {
             case 2: return binned_adjoint<Tag, D, 2>(c);
             case 4: return binned_adjoint<Tag, D, 4>(c);
             case 8: return binned_adjoint<Tag, D, 8>(c);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (c.op == EncodeOp::InputGrad) {
+        switch (c.F) {
+            case 1: return input_grad_dispatch_types<Tag, D, 1>(c);
+            case 2: return input_grad_dispatch_types<Tag, D, 2>(c);
+            case 4: return input_grad_dispatch_types<Tag, D, 4>(c);
+            case 8: return input_grad_dispatch_types<Tag, D, 8>(c);
             default: return hipErrorInvalidValue;
         }
     }

@@ -234,6 +234,96 @@ __global__ __launch_bounds__(kBlock) void encode_twin_kernel(int64_t N, const fl
     }
 }
 
+// ---- gradient with respect to the input point ---------------------------
+// Inside a simplex the weights are affine in the fractional parts: the
+// derivative along the axis stepped between walk vertices k and k+1 is the
+// difference of their rows.  The grid differentiates its n-linear weights,
+// d w_b / d f_i = (b_i ? 1 : -1) prod_{m != i} (b_m ? f_m : 1 - f_m).  The
+// chain to x: d p_i / d x_m = sigma (delta_im + F_n) (skew, Eq. 2) for the
+// simplex and sigma delta_im for the grid.
+template <class Tag, int D, int F, typename TT, typename GT>
+__global__ __launch_bounds__(kBlock) void encode_input_grad_kernel(int64_t N, const float* __restrict__ pts,
+                                                                   const TT* __restrict__ tables,
+                                                                   const GT* __restrict__ d_out,
+                                                                   float* __restrict__ d_pts, LevelArgs lv) {
+    const uint32_t mask = lv.mask;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
+        float y[D];
+        load_point<Tag, D>(pts, pt, lv.Fn, y);
+        const GT* __restrict__ grow = d_out + pt * (int64_t)(lv.L * F);
+        float dx[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) dx[m] = 0.0f;
+        for (int l = 0; l < lv.L; ++l) {
+            const TT* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * F);
+            float d[F], g[D];
+            RowIO<GT, F>::load(grow + l * F, d);
+#pragma unroll
+            for (int m = 0; m < D; ++m) g[m] = 0.0f;
+            if constexpr (Tag::simplex) {
+                visit_level_ex(Tag{}, y, lv.sigma[l], mask,
+                               [&](const auto& h, const auto&, int, const auto&, const auto& offs) {
+                    float t[D + 1][F];
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) RowIO<TT, F>::load(tab + (size_t)h[k] * F, t[k]);
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const int axis = __builtin_ctz(offs[k + 1] ^ offs[k]);
+                        float s = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < F; ++j) s += (t[k + 1][j] - t[k][j]) * d[j];
+#pragma unroll
+                        for (int m = 0; m < D; ++m) g[m] += m == axis ? s : 0.0f;
+                    }
+                });
+            } else {
+                float f[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+#pragma clang fp contract(off)
+                    const float p = y[i] * lv.sigma[l];
+                    f[i] = p - floorf(p);
+                }
+                visit_level_ex(Tag{}, y, lv.sigma[l], mask,
+                               [&](const auto& h, const auto& w, int, const auto&, const auto& offs) {
+                    constexpr int K = sizeof(w) / sizeof(float);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        float t[F];
+                        RowIO<TT, F>::load(tab + (size_t)h[k] * F, t);
+                        float s = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < F; ++j) s += t[j] * d[j];
+                        const uint32_t b = offs[k];
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            float c = ((b >> i) & 1u) ? s : -s;
+#pragma unroll
+                            for (int m = 0; m < D; ++m)
+                                if (m != i) c *= ((b >> m) & 1u) ? f[m] : 1.0f - f[m];
+                            g[i] += c;
+                        }
+                    }
+                });
+            }
+            const float sig = lv.sigma[l];
+            if constexpr (Tag::simplex) {
+                float gs = 0.0f;
+#pragma unroll
+                for (int m = 0; m < D; ++m) gs += g[m];
+#pragma unroll
+                for (int m = 0; m < D; ++m) dx[m] += sig * (g[m] + lv.Fn * gs);
+            } else {
+#pragma unroll
+                for (int m = 0; m < D; ++m) dx[m] += sig * g[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < D; ++m) d_pts[pt * D + m] = dx[m];
+    }
+}
+
 // ---- adjoint ------------------------------------------------------------
 
 template <class Tag, int D, int F, typename GT>

@@ -35,7 +35,7 @@ struct AdamArgs {
     float lr, b1, b2, eps, inv_bc1, inv_bc2;
 };
 
-enum class EncodeOp { Forward, Adjoint, AdjointBinned, Debug, Twin };
+enum class EncodeOp { Forward, Adjoint, AdjointBinned, Debug, Twin, InputGrad };
 
 // Binned adjoint: one level group's plan (device pointers into the caller's
 // workspace).  Levels [0, P) of group 0 are privatised: their contributions

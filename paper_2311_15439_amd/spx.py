@@ -72,6 +72,7 @@ _SIGNATURES = {
                                       C.c_float, C.c_float, C.c_int64, _P, C.c_size_t, _P]),
     "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_encode_gather_twin": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
+    "spx_encode_input_grad": (C.c_int, [_P, C.c_int64, _P, _P, _P, C.c_int32, _P, _P]),
     "spx_composite_fwd": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P]),
     "spx_composite_bwd": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P, _P]),
     "spx_cast_f32_f16": (C.c_int, [C.c_int64, _P, _P, _P]),
@@ -291,6 +292,21 @@ def spx_encode_debug(enc: Encoding, pts, idx=None, w=None, stream=None) -> None:
                                   None if idx is None else _dev(idx, torch.int32, "idx"),
                                   None if w is None else _dev(w, torch.float32, "w"), _stream(stream)),
            "spx_encode_debug")
+
+
+def spx_encode_input_grad(enc: Encoding, pts, tables, d_out, d_pts, stream=None) -> None:
+    """d_pts [N, n] float32 = d_out [N, L*F] contracted with d out / d pts."""
+    torch = _torch()
+    N = pts.shape[0]
+    if pts.shape != (N, enc.n_dims) or tuple(tables.shape) != enc.table_shape or tuple(d_pts.shape) != (N, enc.n_dims):
+        raise ValueError("pts, tables or d_pts shape does not match the encoding")
+    if tuple(d_out.shape) != (N, enc.n_levels * enc.n_feat):
+        raise ValueError("d_out shape must be [N, L*F]")
+    tdt = torch.float16 if enc.table_dtype == SPX_F16 else torch.float32
+    _check(lib().spx_encode_input_grad(enc.ref(), N, _dev(pts, torch.float32, "pts"), _dev(tables, tdt, "tables"),
+                                       _dev(d_out, None, "d_out"), _dtype_code(d_out),
+                                       _dev(d_pts, torch.float32, "d_pts"), _stream(stream)),
+           "spx_encode_input_grad")
 
 
 def spx_encode_gather_twin(enc: Encoding, pts, tables, out, stream=None) -> None:

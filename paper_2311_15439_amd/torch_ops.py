@@ -2,7 +2,8 @@
 
 * ``SimplexEncodingFn``: points -> encoded features (binary32 out), with the
   binary32 master tables as the differentiable input; the forward gathers
-  from their binary16 copy, the backward runs the binned adjoint.
+  from their binary16 copy, the backward runs the binned adjoint (and, when
+  the points require a gradient, the input-gradient kernel).
 * ``MLPFn``: features (binary32) -> network output; weights as binary32
   masters, binary16 copies for the matrix cores.
 * ``FieldFn``: encoding and network together, keeping the binary16 features
@@ -45,19 +46,25 @@ class SimplexEncodingFn(torch.autograd.Function):
         N = pts.shape[0]
         out = torch.empty((N, enc.n_levels * enc.n_feat), dtype=torch.float32, device=pts.device)
         spx.spx_encode_fwd(enc, pts, table_f16, out)
-        ctx.save_for_backward(pts)
+        ctx.save_for_backward(pts, table_f16)
         ctx.enc, ctx.ws = enc, ws
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
-        (pts,) = ctx.saved_tensors
+        pts, table_f16 = ctx.saved_tensors
         enc = ctx.enc
+        g = grad_out.contiguous().float()
         grad = torch.zeros(enc.table_shape, dtype=torch.float32, device=pts.device)
         if pts.shape[0] > 0:
             w = ctx.ws.get(spx.spx_encode_bwd_workspace(enc, pts.shape[0]), pts.device)
-            spx.spx_encode_bwd(enc, pts, grad_out.contiguous().float(), grad, w)
-        return None, grad, None, None, None
+            spx.spx_encode_bwd(enc, pts, g, grad, w)
+        d_pts = None
+        if ctx.needs_input_grad[0]:
+            d_pts = torch.empty_like(pts)
+            if pts.shape[0] > 0:
+                spx.spx_encode_input_grad(enc, pts, table_f16, g, d_pts)
+        return d_pts, grad, None, None, None
 
 
 class MLPFn(torch.autograd.Function):
@@ -92,13 +99,13 @@ class FieldFn(torch.autograd.Function):
         spx.spx_encode_fwd(enc, pts, table_f16, feats)
         y = torch.empty((N, mlp.d_out), dtype=torch.float32, device=pts.device)
         spx.spx_mlp_fwd(mlp, feats, *W16, y)
-        ctx.save_for_backward(pts, feats)
+        ctx.save_for_backward(pts, feats, table_f16)
         ctx.enc, ctx.mlp, ctx.W16, ctx.ws_enc, ctx.ws_mlp = enc, mlp, W16, ws_enc, ws_mlp
         return y
 
     @staticmethod
     def backward(ctx, gy):
-        pts, feats = ctx.saved_tensors
+        pts, feats, table_f16 = ctx.saved_tensors
         enc, mlp, W16 = ctx.enc, ctx.mlp, ctx.W16
         N = pts.shape[0]
         dfeats = torch.empty(feats.shape, dtype=torch.float32, device=pts.device)
@@ -109,7 +116,12 @@ class FieldFn(torch.autograd.Function):
         if N > 0:
             spx.spx_encode_bwd(enc, pts, dfeats, grad,
                                ctx.ws_enc.get(spx.spx_encode_bwd_workspace(enc, N), pts.device))
-        return None, grad, dW[0], dW[1], dW[2], None, None, None, None, None, None
+        d_pts = None
+        if ctx.needs_input_grad[0]:
+            d_pts = torch.empty_like(pts)
+            if N > 0:
+                spx.spx_encode_input_grad(enc, pts, table_f16, dfeats, d_pts)
+        return d_pts, grad, dW[0], dW[1], dW[2], None, None, None, None, None, None
 
 
 class SimplexEncoding(torch.nn.Module):

@@ -101,3 +101,19 @@ def test_small_field_trains(cell):
         opt.step()
         losses.append(loss.item())
     assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:5]), (losses[:5], losses[-20:])
+
+
+def test_encoding_fn_input_gradient():
+    """Points that require a gradient receive d L / d x from the input-gradient
+    kernel, equal to the oracle's for the binary16 tables the forward read."""
+    from paper_2311_15439_amd.torch_ops import SimplexEncoding
+    m = SimplexEncoding(3, n_levels=4, log2_T=14, n_min=8, n_max=200, init_scale=1.0, seed=3)
+    pts = inputs.uniform_points(3000, 3, 12)
+    tp = torch.from_numpy(pts).to(DEV).requires_grad_(True)
+    G = inputs.gradients(3000, 8, 13)
+    (m(tp) * torch.from_numpy(G).to(DEV)).sum().backward()
+    torch.cuda.synchronize()
+    oe = _oracle_enc(m)
+    ref, mag = oracle.encode_input_grad(oe, pts, m.table_f16.cpu().numpy(), G.astype(np.float64), with_mag=True)
+    tol = 2 * (2 + 6 + 4 + 4 + 8) * 2.0 ** -24 * mag + 1e-30
+    assert (np.abs(tp.grad.cpu().numpy() - ref) <= tol).all()
