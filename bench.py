@@ -437,6 +437,17 @@ def time_encode_sweep(reps=30, warm=5):
                 spx.spx_encode_bwd(enc, pts, dout, grad, ws)
                 ev[r][4].record()
             torch.cuda.synchronize()
+            # gradient with respect to the points (same rows as the forward)
+            dpts = torch.empty((N, w.n_dims), dtype=torch.float32, device=dev)
+            ig_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            spx.spx_encode_input_grad(enc, pts, tab, dout, dpts)
+            ig_ev[0].record()
+            for _ in range(10):
+                spx.spx_encode_input_grad(enc, pts, tab, dout, dpts)
+            ig_ev[1].record()
+            torch.cuda.synchronize()
+            input_grad_ms = ig_ev[0].elapsed_time(ig_ev[1]) / 10
+            del dpts
             # one traced adjoint: where its time goes, kernel by kernel
             grad.zero_()
             trace = spx.Trace(capacity=64)
@@ -458,7 +469,7 @@ def time_encode_sweep(reps=30, warm=5):
             V = enc.n_vertices
             gathers = N * w.n_levels * V
             row[cname] = {"fwd": fq, "zero_grad": _quantiles(z), "bwd": _quantiles(b), "fwd_bwd": tq,
-                          "gather_twin": wq, "bwd_kernels": bwd_kernels,
+                          "gather_twin": wq, "bwd_kernels": bwd_kernels, "input_grad_ms": input_grad_ms,
                           "fwd_points_per_s": N / (fq["median_ms"] * 1e-3),
                           "fwd_bwd_points_per_s": N / (tq["median_ms"] * 1e-3),
                           "twin_gathers_per_s": gathers / (wq["median_ms"] * 1e-3),

@@ -255,6 +255,8 @@ __global__ __launch_bounds__(kBlock) void encode_input_grad_kernel(int64_t N, co
         float dx[D];
 #pragma unroll
         for (int m = 0; m < D; ++m) dx[m] = 0.0f;
+        // unrolled so that several levels' gathers are in flight together
+#pragma unroll 4
         for (int l = 0; l < lv.L; ++l) {
             const TT* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * F);
             float d[F], g[D];
