@@ -99,10 +99,11 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
         for (int c = 0; c < kAccPre; ++c) {
             const int i = threadIdx.x + c * kAccBlock;
             if (i < n4) {
-                P[c] = reinterpret_cast<const f32x4*>(base_ptr + off)[i];
+                // read once per step: non-temporal, so they do not displace the records
+                P[c] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(base_ptr + off) + i);
                 if constexpr (ADAM) {
-                    M[c] = reinterpret_cast<const f32x4*>(adam.m + off)[i];
-                    Vv[c] = reinterpret_cast<const f32x4*>(adam.v + off)[i];
+                    M[c] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(adam.m + off) + i);
+                    Vv[c] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(adam.v + off) + i);
                 }
             }
         }
