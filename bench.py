@@ -157,37 +157,55 @@ class TrainStep:
         self.t = 0
         self.lr = 1e-2
         self.fused = fused
-        self.names = ["encode_fwd", "mlp_fwd", "mse_grad", "mlp_bwd",
-                      "encode_bwd_adam" if fused else "encode_bwd", "adam_tables", "adam_mlp"]
+        # the fused encoding + network forward covers 2-/3-D fields of 16 levels x 2 features
+        self.fused_fwd = w.n_dims in (2, 3) and D == 32 and w.n_feat == 2
 
-    def step(self, b, ev=None):
+    @property
+    def names(self):
+        return [n for n, _ in self._calls(0)]
+
+    def _calls(self, b):
+        """The step's library calls in order, as (name, thunk)."""
         spx = self.spx
         pts, tgt = self.batches[b % len(self.batches)]
-        self.t += 1
-        rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
-        rec(0)
-        spx.spx_encode_fwd(self.enc, pts, self.tab16, self.feats)
-        rec(1)
-        spx.spx_mlp_fwd(self.mlp, self.feats, *self.Wv, self.y)
-        rec(2)
-        spx.spx_mse_grad(self.y, tgt, self.dy, 2.0 / (self.N * self.d_out))
-        rec(3)
-        spx.spx_mlp_bwd(self.mlp, self.feats, *self.Wv, self.dy, self.dfeats, *self.dWv, self.ws)
-        rec(4)
+        calls = []
+        if self.fused_fwd:
+            calls.append(("encode_mlp_fwd", lambda: spx.spx_encode_mlp_fwd(self.enc, self.mlp, pts, self.tab16, *self.Wv,
+                                                                           self.y, feats=self.feats)))
+        else:
+            calls.append(("encode_fwd", lambda: spx.spx_encode_fwd(self.enc, pts, self.tab16, self.feats)))
+            calls.append(("mlp_fwd", lambda: spx.spx_mlp_fwd(self.mlp, self.feats, *self.Wv, self.y)))
+        calls += self._loss_calls(b, tgt)
+        calls.append(("mlp_bwd", lambda: spx.spx_mlp_bwd(self.mlp, self.feats, *self.Wv, self.dy, self.dfeats,
+                                                         *self.dWv, self.ws)))
         if self.fused:
             # adjoint and Adam on the tables in one pass (no gradient table)
-            spx.spx_encode_bwd_adam(self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr,
-                                    beta1=0.9, beta2=0.99, eps=1e-15, step=self.t, workspace=self.bws)
-            rec(5)
+            calls.append(("encode_bwd_adam", lambda: spx.spx_encode_bwd_adam(
+                self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9,
+                beta2=0.99, eps=1e-15, step=self.t, workspace=self.bws)))
         else:
-            spx.spx_encode_bwd(self.enc, pts, self.dfeats, self.grad, self.bws)
-            rec(5)
-            spx.spx_adam_step(self.master, self.grad, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9, beta2=0.99,
-                              eps=1e-15, step=self.t, zero_grad=True)
-        rec(6)
-        spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=self.lr, beta1=0.9, beta2=0.99,
-                          eps=1e-15, step=self.t, zero_grad=False)
-        rec(7)
+            calls.append(("encode_bwd", lambda: spx.spx_encode_bwd(self.enc, pts, self.dfeats, self.grad, self.bws)))
+            calls.append(("adam_tables", lambda: spx.spx_adam_step(
+                self.master, self.grad, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9, beta2=0.99, eps=1e-15,
+                step=self.t, zero_grad=True)))
+        calls.append(("adam_mlp", lambda: spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=self.lr,
+                                                            beta1=0.9, beta2=0.99, eps=1e-15, step=self.t,
+                                                            zero_grad=False)))
+        return calls
+
+    def _loss_calls(self, b, tgt):
+        spx = self.spx
+        return [("mse_grad", lambda: spx.spx_mse_grad(self.y, tgt, self.dy, 2.0 / (self.N * self.d_out)))]
+
+    def step(self, b, ev=None):
+        self.t += 1
+        calls = self._calls(b)
+        for i, (_, fn) in enumerate(calls):
+            if ev is not None:
+                ev[i].record()
+            fn()
+        if ev is not None:
+            ev[len(calls)].record()
 
     def algorithmic_bytes(self):
         """Bytes each kernel must move per launch (what the method reads and
@@ -200,6 +218,7 @@ class TrainStep:
         D = L * F
         return {
             "encode_fwd": N * (4 * n + L * V * F * 2 + D * 2),
+            "encode_mlp_fwd": N * (4 * n + L * V * F * 2 + D * 2 + 4 * self.d_out),
             "mlp_fwd": N * (2 * D + 4 * self.d_out),
             "mse_grad": N * self.d_out * 12,
             "mlp_bwd": N * (2 * D + 4 * self.d_out + 4 * D),
@@ -231,35 +250,14 @@ class RenderStep(TrainStep):
         self.deltas = [torch.from_numpy(d.reshape(self.R, self.S)).to("cuda") for _, d, _ in batches]
         self.rgba = torch.empty((self.R, 4), dtype=torch.float32, device="cuda")
         self.drgba = torch.empty_like(self.rgba)
-        self.names = ["encode_fwd", "mlp_fwd", "composite_fwd", "mse_grad", "composite_bwd", "mlp_bwd",
-                      "encode_bwd_adam", "adam_mlp"]
 
-    def step(self, b, ev=None):
+    def _loss_calls(self, b, tgt):
         spx = self.spx
-        pts, tgt = self.batches[b % len(self.batches)]
         delta = self.deltas[b % len(self.deltas)]
-        self.t += 1
-        rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
         raw = self.y.view(self.R, self.S, 4)
-        rec(0)
-        spx.spx_encode_fwd(self.enc, pts, self.tab16, self.feats)
-        rec(1)
-        spx.spx_mlp_fwd(self.mlp, self.feats, *self.Wv, self.y)
-        rec(2)
-        spx.spx_composite_fwd(raw, delta, self.rgba)
-        rec(3)
-        spx.spx_mse_grad(self.rgba, tgt, self.drgba, 2.0 / (self.R * 4))
-        rec(4)
-        spx.spx_composite_bwd(raw, delta, self.drgba, self.dy.view(self.R, self.S, 4))
-        rec(5)
-        spx.spx_mlp_bwd(self.mlp, self.feats, *self.Wv, self.dy, self.dfeats, *self.dWv, self.ws)
-        rec(6)
-        spx.spx_encode_bwd_adam(self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr,
-                                beta1=0.9, beta2=0.99, eps=1e-15, step=self.t, workspace=self.bws)
-        rec(7)
-        spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=self.lr, beta1=0.9, beta2=0.99,
-                          eps=1e-15, step=self.t, zero_grad=False)
-        rec(8)
+        return [("composite_fwd", lambda: spx.spx_composite_fwd(raw, delta, self.rgba)),
+                ("mse_grad", lambda: spx.spx_mse_grad(self.rgba, tgt, self.drgba, 2.0 / (self.R * 4))),
+                ("composite_bwd", lambda: spx.spx_composite_bwd(raw, delta, self.drgba, self.dy.view(self.R, self.S, 4)))]
 
 
 def _render_batch(w, b, n_samples):
@@ -579,6 +577,34 @@ def time_stream_reference(ts, reps=10):
     return {"adam_ms": a, "adam_GB_s": P * 36 / (a * 1e-3) / 1e9, "cast_ms": c, "cast_GB_s": P * 6 / (c * 1e-3) / 1e9}
 
 
+def time_fused_query(ts, reps=20):
+    """The serving kernel (encoding and network forward fused, features kept
+    in registers) on the step's first batch, against the separate encode
+    forward and network forward kernels."""
+    import torch
+    spx = ts.spx
+    pts, _ = ts.batches[0]
+    field = spx.spx_field_init(ts.enc, ts.tab16, *ts.Wv, ts.d_out)
+    fdev = torch.frombuffer(bytearray(spx.as_bytes([field])), dtype=torch.uint8).cuda()
+    seg = spx.spx_segment()
+    seg.pts, seg.out, seg.count, seg.first_tile, seg.field = pts.data_ptr(), ts.y.data_ptr(), ts.N, 0, 0
+    sdev = torch.frombuffer(bytearray(spx.as_bytes([seg])), dtype=torch.uint8).cuda()
+    tiles = (ts.N + 15) // 16
+    for _ in range(3):
+        spx.spx_field_query_batched(fdev, 1, sdev, 1, tiles)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        spx.spx_field_query_batched(fdev, 1, sdev, 1, tiles)
+    e[1].record()
+    for _ in range(reps):
+        spx.spx_encode_fwd(ts.enc, pts, ts.tab16, ts.feats)
+        spx.spx_mlp_fwd(ts.mlp, ts.feats, *ts.Wv, ts.y)
+    e[2].record()
+    torch.cuda.synchronize()
+    return {"fused_ms": e[0].elapsed_time(e[1]) / reps, "separate_ms": e[1].elapsed_time(e[2]) / reps}
+
+
 def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
     """The oracle (as it stands) on a bounded sample of the same step: the
     per-point work on S points, Adam on 1/16 of the tables; scaled to one
@@ -764,6 +790,7 @@ def main():
     ms, per, wall, kern = time_steps(ts, args.steps, args.warmup)
     enc_s = time_encode_only(ts)
     stream = time_stream_reference(ts)
+    fused_query = time_fused_query(ts)
     bytes_ = ts.algorithmic_bytes()
     per = {k: v for k, v in per.items() if bytes_.get(k, 0) > 0}
     # dominant single kernel of the step (total time per step), from the trace
@@ -844,6 +871,7 @@ def main():
         "grid_baseline_step": ({"points_per_s": grid["step_points_per_s"], "ms_per_step": grid["ms_per_step"],
                                 "kernels_ms": grid["kernels_ms"]} if grid else None),
         "stream_reference": stream,
+        "fused_query": fused_query,
         "encode_sweep": sweep,
         "equal_accuracy": accuracy,
         "volume_step": volume,

@@ -411,6 +411,25 @@ spx_status spx_field_init(const spx_encoding* enc, const void* tables, const uin
 spx_status spx_field_query_batched(const spx_field* fields, int32_t nfields, const spx_segment* segs, int32_t nseg,
                                    int64_t total_tiles, hipStream_t stream);
 
+/*
+ * Encoding forward and network forward in one kernel, for training (Sec. 5
+ * steps (a)-(e) forward): the same configurations as spx_field_init (2- or
+ * 3-D, 16 levels of 2 binary16 features, a 32-64-64-d_out network, d_out
+ * 1..16).  Per 16-point tile each lane encodes four levels of one point,
+ * which are exactly its operand of the network's first matrix product, so
+ * the features go from the gathers to the matrix cores in registers; they
+ * are also stored (if feats is not NULL) for the network's backward.
+ *   feats  device [N][32] binary16, 16-byte aligned, or NULL: identical to
+ *          spx_encode_fwd with a binary16 output.
+ *   out    device [N][d_out] binary32, 4-byte aligned: identical to
+ *          spx_mlp_fwd of those features.
+ * Other arguments as spx_encode_fwd and spx_mlp_fwd; unsupported
+ * configurations return SPX_EUNSUPPORTED.
+ */
+spx_status spx_encode_mlp_fwd(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, const float* pts,
+                              const void* tables, const uint16_t* W1, const uint16_t* W2, const uint16_t* W3,
+                              uint16_t* feats, float* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

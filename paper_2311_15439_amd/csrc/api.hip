@@ -420,6 +420,21 @@ spx_status spx_field_init(const spx_encoding* enc, const void* tables, const uin
     return SPX_OK;
 }
 
+spx_status spx_encode_mlp_fwd(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, const float* pts,
+                              const void* tables, const uint16_t* W1, const uint16_t* W2, const uint16_t* W3,
+                              uint16_t* feats, float* out, hipStream_t stream) {
+    if (!mlp) return fail(SPX_EINVAL, "mlp descriptor is NULL");
+    if (mlp->d_in != 32 || mlp->hidden != 64) return fail(SPX_EUNSUPPORTED, "the fused forward is built for 32-64-64-d_out");
+    spx_field f;
+    spx_status st = spx_field_init(enc, tables, W1, W2, W3, mlp->d_out, &f);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (N == 0) return SPX_OK;
+    if (!out) return fail(SPX_EINVAL, "out is NULL");
+    if (!aligned(out, 4) || (feats && !aligned(feats, 16))) return fail(SPX_EALIGN, "out 4-byte, feats 16-byte aligned");
+    return from_hip(spx::encode_mlp_fwd(f, N, pts, out, feats, stream), "spx_encode_mlp_fwd launch");
+}
+
 spx_status spx_field_query_batched(const spx_field* fields, int32_t nfields, const spx_segment* segs, int32_t nseg,
                                    int64_t total_tiles, hipStream_t stream) {
     if (nfields < 0 || nseg < 0 || total_tiles < 0) return fail(SPX_EINVAL, "negative count");

@@ -81,11 +81,16 @@ __device__ __forceinline__ h8 encode_quarter(const spx_field& f, const float* __
     return out;
 }
 
+// One tile of 16 points: encode (lane (r, q) holds features 8q..8q+7 of
+// point r), optionally store the binary16 features, run the network, store
+// the outputs.
 template <class Tag, int D>
-__device__ __forceinline__ void run_tile(const spx_field& f, const Weights& W, const spx_segment& seg, int64_t p,
-                                         int r, int q) {
-    const bool valid = p >= 0 && p < seg.count;
-    const h8 xb = encode_quarter<Tag, D>(f, seg.pts + (valid ? p : 0) * D, valid, q);
+__device__ __forceinline__ void fwd_tile(const spx_field& f, const Weights& W, const float* __restrict__ pts,
+                                         int64_t count, int64_t p, int r, int q, float* __restrict__ out,
+                                         _Float16* __restrict__ feats) {
+    const bool valid = p >= 0 && p < count;
+    const h8 xb = encode_quarter<Tag, D>(f, pts + (valid ? p : 0) * D, valid, q);
+    if (feats && valid) *reinterpret_cast<h8*>(feats + p * 32 + 8 * q) = xb;
     h4 h1[4], h2[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) h1[t] = relu_h(mma_h(W.w1[t], xb, f4{0.f, 0.f, 0.f, 0.f}));
@@ -102,7 +107,30 @@ __device__ __forceinline__ void run_tile(const spx_field& f, const Weights& W, c
     if (valid) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (4 * q + i < f.d_out) seg.out[p * f.d_out + 4 * q + i] = o[i];
+            if (4 * q + i < f.d_out) out[p * f.d_out + 4 * q + i] = o[i];
+    }
+}
+
+template <class Tag, int D>
+__device__ __forceinline__ void run_tile(const spx_field& f, const Weights& W, const spx_segment& seg, int64_t p,
+                                         int r, int q) {
+    fwd_tile<Tag, D>(f, W, seg.pts, seg.count, p, r, q, seg.out, nullptr);
+}
+
+// Training forward: one field, N points, tiles of 16 points handed to waves
+// in contiguous runs; the binary16 features are kept for the backward.
+template <class Tag, int D>
+__global__ __launch_bounds__(256) void encode_mlp_fwd_kernel(spx_field f, int64_t N, const float* __restrict__ pts,
+                                                             float* __restrict__ out, _Float16* __restrict__ feats) {
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t tiles = (N + 15) / 16;
+    Weights W;
+    load_weights(f, r, q, W);
+    for (int64_t t0 = wave * kTilesPerWave; t0 < tiles; t0 += nwaves * kTilesPerWave) {
+        const int64_t t1 = t0 + kTilesPerWave < tiles ? t0 + kTilesPerWave : tiles;
+        for (int64_t t = t0; t < t1; ++t) fwd_tile<Tag, D>(f, W, pts, N, t * 16 + r, r, q, out, feats);
     }
 }
 
@@ -143,6 +171,27 @@ __global__ __launch_bounds__(256) void field_query_kernel(const spx_field* __res
 }
 
 }  // namespace
+
+hipError_t encode_mlp_fwd(const spx_field& f, int64_t N, const float* pts, float* out, uint16_t* feats,
+                          hipStream_t s) {
+    const int64_t tiles = (N + 15) / 16;
+    const int64_t waves = (tiles + kTilesPerWave - 1) / kTilesPerWave;
+    int64_t blocks = (waves + 3) / 4;
+    blocks = blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192;
+    const int V = f.cell == SPX_GRID ? (1 << f.n_dims) : f.n_dims + 1;
+    trace_begin(s, "encode_mlp_fwd",
+                (double)N * (4.0 * f.n_dims + 16.0 * V * 4.0 + 4.0 * f.d_out + (feats ? 64.0 : 0.0)));
+    _Float16* fe = (_Float16*)feats;
+    if (f.cell == SPX_GRID) {
+        if (f.n_dims == 2) encode_mlp_fwd_kernel<GridTag, 2><<<(unsigned)blocks, 256, 0, s>>>(f, N, pts, out, fe);
+        else encode_mlp_fwd_kernel<GridTag, 3><<<(unsigned)blocks, 256, 0, s>>>(f, N, pts, out, fe);
+    } else {
+        if (f.n_dims == 2) encode_mlp_fwd_kernel<SimplexTag, 2><<<(unsigned)blocks, 256, 0, s>>>(f, N, pts, out, fe);
+        else encode_mlp_fwd_kernel<SimplexTag, 3><<<(unsigned)blocks, 256, 0, s>>>(f, N, pts, out, fe);
+    }
+    trace_end(s);
+    return hipGetLastError();
+}
 
 hipError_t field_query(const spx_field* fields, int nfields, const spx_segment* segs, int nseg, int64_t total_tiles,
                        hipStream_t s) {

@@ -319,27 +319,31 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
     }
 }
 
-// Sum the per-group partials and scatter into dW1/dW2/dW3.  A block owns 64
-// outputs; its four thread groups each sum a contiguous quarter of the
-// groups, and the quarters are added in order, so the result does not depend
-// on scheduling.
+// Sum of the per-workgroup weight-gradient partials.  A block owns 32
+// outputs; 32 thread rows each add a contiguous segment of the workgroups'
+// partials in order, and the segment sums are then added in order, so the
+// result does not depend on scheduling.
+constexpr int kRedOut = 32, kRedSeg = 32;
 template <int DIN>
-__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int groups, int d_out,
-                                                         float* __restrict__ dW1, float* __restrict__ dW2,
-                                                         float* __restrict__ dW3) {
+__global__ __launch_bounds__(kRedOut * kRedSeg) void mlp_reduce_kernel(const float* __restrict__ partial, int groups,
+                                                                      int d_out, float* __restrict__ dW1,
+                                                                      float* __restrict__ dW2,
+                                                                      float* __restrict__ dW3) {
     constexpr int PARTIAL = BwdLayout<DIN>::PARTIAL;
-    __shared__ float part[4][64];
-    const int o = threadIdx.x & 63, qd = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + o;
-    const int per = (groups + 3) / 4;
-    const int g0 = qd * per, g1 = g0 + per < groups ? g0 + per : groups;
+    __shared__ float part[kRedSeg][kRedOut];
+    const int o = threadIdx.x % kRedOut, sg = threadIdx.x / kRedOut;
+    const int i = blockIdx.x * kRedOut + o;
+    const int per = (groups + kRedSeg - 1) / kRedSeg;
+    const int g0 = sg * per < groups ? sg * per : groups;
+    const int g1 = g0 + per < groups ? g0 + per : groups;
     float s = 0.0f;
     if (i < PARTIAL)
         for (int g = g0; g < g1; ++g) s += partial[(size_t)g * PARTIAL + i];
-    part[qd][o] = s;
+    part[sg][o] = s;
     __syncthreads();
-    if (qd != 0 || i >= PARTIAL) return;
-    s = ((part[0][o] + part[1][o]) + part[2][o]) + part[3][o];
+    if (sg != 0 || i >= PARTIAL) return;
+    s = part[0][o];
+    for (int k = 1; k < kRedSeg; ++k) s += part[k][o];
     if (i < H * DIN) {
         dW1[i] = s;
     } else if (i < H * DIN + H * H) {
@@ -383,7 +387,8 @@ hipError_t bwd_impl(const MlpCall& c) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     trace_begin(c.stream, "mlp_reduce", ((double)g + 1.0) * Lay::PARTIAL * 4.0);
-    mlp_reduce_kernel<DIN><<<(Lay::PARTIAL + 63) / 64, 256, 0, c.stream>>>(part, g, c.d_out, c.dW1, c.dW2, c.dW3);
+    mlp_reduce_kernel<DIN><<<(Lay::PARTIAL + kRedOut - 1) / kRedOut, kRedOut * kRedSeg, 0, c.stream>>>(
+        part, g, c.d_out, c.dW1, c.dW2, c.dW3);
     trace_end(c.stream);
     return hipGetLastError();
 }

@@ -202,6 +202,8 @@ hipError_t field_query(const spx_field* fields, int nfields, const spx_segment* 
                        hipStream_t s);
 hipError_t mse_grad(int64_t n, const float* y, const float* target, float* d_y, float scale, hipStream_t s);
 hipError_t cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t s);
+hipError_t encode_mlp_fwd(const spx_field& f, int64_t N, const float* pts, float* out, uint16_t* feats,
+                          hipStream_t s);
 hipError_t composite_fwd(int64_t R, int S, const float* raw, const float* delta, float* rgba, hipStream_t s);
 hipError_t composite_bwd(int64_t R, int S, const float* raw, const float* delta, const float* d_rgba, float* d_raw,
                          hipStream_t s);

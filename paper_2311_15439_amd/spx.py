@@ -73,6 +73,7 @@ _SIGNATURES = {
     "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_encode_gather_twin": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_encode_input_grad": (C.c_int, [_P, C.c_int64, _P, _P, _P, C.c_int32, _P, _P]),
+    "spx_encode_mlp_fwd": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "spx_composite_fwd": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P]),
     "spx_composite_bwd": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P, _P]),
     "spx_cast_f32_f16": (C.c_int, [C.c_int64, _P, _P, _P]),
@@ -434,6 +435,22 @@ def spx_field_init(enc: Encoding, tables, W1, W2, W3, d_out: int) -> spx_field:
     _check(lib().spx_field_init(enc.ref(), _dev(tables, h, "tables"), _dev(W1, h, "W1"), _dev(W2, h, "W2"),
                                 _dev(W3, h, "W3"), int(d_out), C.byref(out)), "spx_field_init")
     return out
+
+
+def spx_encode_mlp_fwd(enc: Encoding, mlp: "spx_mlp", pts, tables, W1, W2, W3, out, feats=None, stream=None) -> None:
+    """Fused training forward: out [N, d_out] float32 (and feats [N, 32]
+    float16 if given) from pts [N, n]."""
+    torch = _torch()
+    N = pts.shape[0]
+    if pts.shape != (N, enc.n_dims) or tuple(tables.shape) != enc.table_shape:
+        raise ValueError("pts or tables shape does not match the encoding")
+    if tuple(out.shape) != (N, mlp.d_out) or (feats is not None and tuple(feats.shape) != (N, 32)):
+        raise ValueError("out must be [N, d_out] and feats [N, 32]")
+    h = torch.float16
+    _check(lib().spx_encode_mlp_fwd(enc.ref(), C.byref(mlp), N, _dev(pts, torch.float32, "pts"),
+                                    _dev(tables, h, "tables"), _dev(W1, h, "W1"), _dev(W2, h, "W2"),
+                                    _dev(W3, h, "W3"), None if feats is None else _dev(feats, h, "feats"),
+                                    _dev(out, torch.float32, "out"), _stream(stream)), "spx_encode_mlp_fwd")
 
 
 def as_bytes(structs) -> bytes:

@@ -96,9 +96,13 @@ class FieldFn(torch.autograd.Function):
     def forward(ctx, pts, params, W1, W2, W3, enc, table_f16, mlp, W16, ws_enc, ws_mlp):
         N = pts.shape[0]
         feats = torch.empty((N, enc.n_levels * enc.n_feat), dtype=torch.float16, device=pts.device)
-        spx.spx_encode_fwd(enc, pts, table_f16, feats)
         y = torch.empty((N, mlp.d_out), dtype=torch.float32, device=pts.device)
-        spx.spx_mlp_fwd(mlp, feats, *W16, y)
+        if enc.n_dims in (2, 3) and enc.n_levels == 16 and enc.n_feat == 2 and mlp.d_in == 32:
+            # one kernel: features go from the gathers to the matrix cores in registers
+            spx.spx_encode_mlp_fwd(enc, mlp, pts, table_f16, *W16, y, feats=feats)
+        else:
+            spx.spx_encode_fwd(enc, pts, table_f16, feats)
+            spx.spx_mlp_fwd(mlp, feats, *W16, y)
         ctx.save_for_backward(pts, feats, table_f16)
         ctx.enc, ctx.mlp, ctx.W16, ctx.ws_enc, ctx.ws_mlp = enc, mlp, W16, ws_enc, ws_mlp
         return y
