@@ -8,6 +8,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "spx.h"
 #include "lookup.hpp"
 #include "spx_internal.h"
@@ -29,6 +31,27 @@ void trace_end(hipStream_t s) {
     if (!t || t->count >= t->capacity) return;
     hipEventRecord(t->events[2 * t->count + 1], s);
     t->count += 1;
+}
+
+// Side stream per device for work that can run beside the main stream
+// (created on first use, default priority).  Callers hold the returned lock
+// while they fork to it and join back, so concurrent callers do not share
+// the fork/join events mid-sequence.
+static std::mutex g_aux_mu;
+static AuxStream g_aux[64];
+
+AuxStream* aux_stream(std::unique_lock<std::mutex>& lock) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    lock = std::unique_lock<std::mutex>(g_aux_mu);
+    AuxStream& a = g_aux[dev];
+    if (!a.s) {
+        if (hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking) != hipSuccess) { a.s = nullptr; return nullptr; }
+        if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess)
+            return nullptr;
+    }
+    return &a;
 }
 
 }  // namespace spx

@@ -457,15 +457,28 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
     trace_end(c.stream);
+    // The privatised coarse levels depend only on the points and the output
+    // gradient, and their sums are needed only by the accumulation: they run
+    // on a side stream beside count / scan / scatter (LDS-atomic bound beside
+    // store bound) and are joined before the accumulation.
+    std::unique_lock<std::mutex> aux_lock;
+    AuxStream* aux = nullptr;
     if (p.P > 0) {
+        aux = aux_stream(aux_lock);
+        hipStream_t cs = c.stream;
+        if (aux) {
+            hipEventRecord(aux->fork, c.stream);
+            hipStreamWaitEvent(aux->s, aux->fork, 0);
+            cs = aux->s;
+        }
         const int n = p.Dtot * F;
-        trace_begin(c.stream, "bin_coarse", N * (4.0 * D + p.P * F * gs) + (double)p.W * n * 4.0);
-        bin_coarse_kernel<Tag, D, F, GT><<<p.W, kBinBlock, (size_t)n * sizeof(float), c.stream>>>(c.N, c.pts, d_out,
-                                                                                                c.lv, p);
-        trace_end(c.stream);
-        trace_begin(c.stream, "bin_coarse_reduce", ((double)p.W + 1.0) * n * 4.0);
-        bin_coarse_reduce_kernel<<<(n + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, n);
-        trace_end(c.stream);
+        trace_begin(cs, "bin_coarse", N * (4.0 * D + p.P * F * gs) + (double)p.W * n * 4.0);
+        bin_coarse_kernel<Tag, D, F, GT><<<p.W, kBinBlock, (size_t)n * sizeof(float), cs>>>(c.N, c.pts, d_out, c.lv, p);
+        trace_end(cs);
+        trace_begin(cs, "bin_coarse_reduce", ((double)p.W + 1.0) * n * 4.0);
+        bin_coarse_reduce_kernel<<<(n + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, cs>>>(p, n);
+        trace_end(cs);
+        if (aux) hipEventRecord(aux->join, aux->s);
     }
     trace_begin(c.stream, "bin_colscan", 2.0 * counts + 4.0 * p.B);
     bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
@@ -487,6 +500,7 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
         bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv,
                                                                                                 p);
     trace_end(c.stream);
+    if (aux) hipStreamWaitEvent(c.stream, aux->join, 0);
     return launch_accum<D, F>(c, p, recs);
 }
 

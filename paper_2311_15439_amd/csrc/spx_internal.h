@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "spx.h"
 
 namespace spx {
@@ -12,6 +14,14 @@ namespace spx {
 // Tracing hooks (no-ops unless a trace is set on the calling thread).
 void trace_begin(hipStream_t s, const char* name, double bytes);
 void trace_end(hipStream_t s);
+
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+// The current device's side stream (nullptr if unavailable); lock is held
+// on return and must be kept until the fork/join sequence is issued.
+AuxStream* aux_stream(std::unique_lock<std::mutex>& lock);
 
 struct SimplexTag { static constexpr bool simplex = true; };
 struct GridTag { static constexpr bool simplex = false; };

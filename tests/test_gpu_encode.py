@@ -358,3 +358,26 @@ def test_bwd_adam_fused_parity(n, res, log2_T, N, cell):
         assert (err <= tol).all(), f"{name}: worst err/tol {np.max(err / tol):.3f}"
     np.testing.assert_array_equal(th.cpu().numpy().view(np.uint16).ravel(),
                                   oracle.cast_f32_f16(gp.astype(np.float32)))
+
+
+def test_bwd_adam_fused_without_points():
+    """No points: every table entry still takes its Adam step with a zero
+    gradient (m and v decay), bit for bit as the standalone Adam kernel."""
+    g, _ = _enc_pair(3, [4, 16, 64, 200], 13, 2, True)
+    shape = g.table_shape
+    rng = np.random.default_rng(34)
+    p0 = (rng.normal(size=shape) * 1e-2).astype(np.float32)
+    m0 = (rng.normal(size=shape) * 1e-3).astype(np.float32)
+    v0 = (rng.random(shape) * 1e-5 + 1e-7).astype(np.float32)
+    kw = dict(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, step=3)
+    a = [torch.from_numpy(x.copy()).to(DEV) for x in (p0, m0, v0)]
+    ha = torch.empty(shape, dtype=torch.float16, device=DEV)
+    ws = torch.empty(max(spx.spx_encode_bwd_workspace(g, 0), 256), dtype=torch.uint8, device=DEV)
+    spx.spx_encode_bwd_adam(g, torch.empty((0, 3), device=DEV), torch.empty((0, 8), device=DEV), *a, ha,
+                            workspace=ws, **kw)
+    b = [torch.from_numpy(x.copy()).to(DEV) for x in (p0, m0, v0)]
+    hb = torch.empty(shape, dtype=torch.float16, device=DEV)
+    spx.spx_adam_step(b[0], torch.zeros(shape, device=DEV), b[1], b[2], hb, zero_grad=False, **kw)
+    torch.cuda.synchronize()
+    for x, y in zip(a + [ha], b + [hb]):
+        assert torch.equal(x, y)
