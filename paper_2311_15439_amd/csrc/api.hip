@@ -46,10 +46,21 @@ AuxStream* aux_stream(std::unique_lock<std::mutex>& lock) {
     lock = std::unique_lock<std::mutex>(g_aux_mu);
     AuxStream& a = g_aux[dev];
     if (!a.s) {
-        if (hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking) != hipSuccess) { a.s = nullptr; return nullptr; }
-        if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess)
+        hipStream_t st = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(st);
             return nullptr;
+        }
+        if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+            (void)hipEventDestroy(fork);
+            (void)hipStreamDestroy(st);
+            return nullptr;
+        }
+        a.s = st;
+        a.fork = fork;
+        a.join = join;
     }
     return &a;
 }

@@ -466,11 +466,10 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     if (p.P > 0) {
         aux = aux_stream(aux_lock);
         hipStream_t cs = c.stream;
-        if (aux) {
-            hipEventRecord(aux->fork, c.stream);
-            hipStreamWaitEvent(aux->s, aux->fork, 0);
-            cs = aux->s;
-        }
+        if (aux && (hipEventRecord(aux->fork, c.stream) != hipSuccess ||
+                    hipStreamWaitEvent(aux->s, aux->fork, 0) != hipSuccess))
+            aux = nullptr;  // run the coarse levels in order on the caller's stream
+        if (aux) cs = aux->s;
         const int n = p.Dtot * F;
         trace_begin(cs, "bin_coarse", N * (4.0 * D + p.P * F * gs) + (double)p.W * n * 4.0);
         bin_coarse_kernel<Tag, D, F, GT><<<p.W, kBinBlock, (size_t)n * sizeof(float), cs>>>(c.N, c.pts, d_out, c.lv, p);
@@ -478,7 +477,10 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
         trace_begin(cs, "bin_coarse_reduce", ((double)p.W + 1.0) * n * 4.0);
         bin_coarse_reduce_kernel<<<(n + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, cs>>>(p, n);
         trace_end(cs);
-        if (aux) hipEventRecord(aux->join, aux->s);
+        if (aux) {
+            const hipError_t e = hipEventRecord(aux->join, aux->s);
+            if (e != hipSuccess) return e;
+        }
     }
     trace_begin(c.stream, "bin_colscan", 2.0 * counts + 4.0 * p.B);
     bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
@@ -500,7 +502,10 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
         bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv,
                                                                                                 p);
     trace_end(c.stream);
-    if (aux) hipStreamWaitEvent(c.stream, aux->join, 0);
+    if (aux) {
+        const hipError_t e = hipStreamWaitEvent(c.stream, aux->join, 0);
+        if (e != hipSuccess) return e;
+    }
     return launch_accum<D, F>(c, p, recs);
 }
 

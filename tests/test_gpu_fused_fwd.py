@@ -17,7 +17,7 @@ def test_fused_forward_equals_separate(n, cell, d_out):
     mlp = spx.make_mlp(32, 64, d_out)
     tab = torch.from_numpy(inputs.tables(16, 1 << 18, 2, 0.5, 60 + n, True)).cuda()
     W = [torch.from_numpy(w).cuda() for w in inputs.mlp_weights(32, 64, d_out, 61)]
-    for N in [1, 15, 16, 17, 1000, 65539]:
+    for N in [1, 15, 16, 17, 1000, 65539, 1 << 20]:
         pts = torch.from_numpy(np.concatenate([inputs.uniform_points(N - 1, n, 62 + N),
                                                np.full((1, n), 1.0, np.float32)])).cuda()
         f_sep = torch.empty((N, 32), dtype=torch.float16, device="cuda")
