@@ -366,6 +366,8 @@ class GpuBackend:
         return ev.query()
 
     def result(self, h) -> np.ndarray:
+        """A view of the downloaded result in the pinned mirror; valid until
+        its arena range is released (the server copies it out first)."""
         _, off, shape = h
         n = int(np.prod(shape)) * 4
-        return self.host_out[off:off + n].numpy().view(np.float32).reshape(shape).copy()
+        return self.host_out[off:off + n].numpy().view(np.float32).reshape(shape)
