@@ -15,12 +15,19 @@
 //            records start;
 //   scatter  each workgroup recomputes its points' lookups and writes one
 //            record {slot within the bucket, w * d_out[F]} per contribution
-//            into its reserved range of the bucket (LDS cursors);
+//            into its reserved range of the bucket: staged in LDS in bucket
+//            order so that each bucket's records leave as a contiguous run
+//            (the direct kernel, for shapes the staging does not fit, keeps
+//            one LDS cursor per bucket);
+//   coarse   levels whose whole vertex box fits in LDS are summed densely
+//            per workgroup instead (no records, no hot buckets), on a side
+//            stream beside the three kernels above;
 //   accum    one workgroup per bucket adds its records into an LDS copy of
 //            the bucket's 2^s slots, then adds that slice to d_tables with
 //            coalesced read-modify-write (each slot is owned by exactly one
 //            workgroup) -- or, in the fused variant, applies the Adam step
-//            to the slice directly, so no gradient table is stored at all.
+//            to the slice directly, so no gradient table is stored at all
+//            (binned_accum.hpp).
 // Levels are processed in groups when the bucket count or the record count
 // of all levels together would not fit.
 #pragma once
