@@ -23,6 +23,7 @@ chunking, back-pressure and failure handling without a GPU.
 from __future__ import annotations
 
 import collections
+import itertools
 import threading
 import time
 from dataclasses import dataclass, field
@@ -120,14 +121,18 @@ class Server:
         self.arena = Arena(arena_bytes)
         backend.alloc_arena(arena_bytes)
         self.chunk_points, self.batch_points, self.max_inflight = chunk_points, batch_points, max_inflight
-        self.lock = threading.Condition()
+        # Clients hand chunks over through `incoming` (a deque: appends and
+        # pops are atomic) and wake the scheduler; only the scheduler thread
+        # touches the other queues, so submitting never waits for it.
+        self.incoming: collections.deque = collections.deque()
+        self._wake = threading.Event()
         self.pending: collections.deque = collections.deque()   # chunks waiting for memory
         self.uploading: List[Chunk] = []
         self.ready: List[Chunk] = []
         self.inflight: List[tuple] = []                           # (handle, chunks)
         self.downloading: List[Chunk] = []
         self.completed: List[Request] = []
-        self._next = 0
+        self._ids = itertools.count()
         self._stop = False
         self._thread: Optional[threading.Thread] = None
         self.batches = 0
@@ -138,9 +143,7 @@ class Server:
     def submit(self, field_id: int, pts: np.ndarray, timeout: Optional[float] = None) -> Request:
         pts = np.ascontiguousarray(pts, np.float32)
         now = time.perf_counter()
-        with self.lock:
-            rid = self._next
-            self._next += 1
+        rid = next(self._ids)
         if not (0 <= field_id < len(self.dims)):
             r = Request(rid, field_id, pts, now, None, error=f"unknown field {field_id}")
             r.t_done = now
@@ -150,16 +153,18 @@ class Server:
             raise ValueError(f"points must be [m, {self.dims[field_id]}]")
         m = pts.shape[0]
         r = Request(rid, field_id, pts, now, None if timeout is None else now + timeout)
-        r.out = np.empty((m, self.outs[field_id]), np.float32)
+        # fault the result's pages in here, on the client's thread: a first
+        # touch by the scheduler's copy would run at page-fault speed
+        r.out = np.zeros((m, self.outs[field_id]), np.float32)
+        r.out.fill(0.0)
         chunks = [Chunk(r, lo, min(lo + self.chunk_points, m)) for lo in range(0, m, self.chunk_points)]
         r.chunks_left = len(chunks)
         if not chunks:
             r.t_done = now
             r._event.set()
             return r
-        with self.lock:
-            self.pending.extend(chunks)
-            self.lock.notify()
+        self.incoming.extend(chunks)
+        self._wake.set()
         return r
 
     # ------------------------------------------------------------- scheduler
@@ -170,9 +175,8 @@ class Server:
         return self
 
     def stop(self) -> None:
-        with self.lock:
-            self._stop = True
-            self.lock.notify()
+        self._stop = True
+        self._wake.set()
         if self._thread:
             self._thread.join()
 
@@ -273,16 +277,16 @@ class Server:
         return progress
 
     def _loop(self) -> None:
-        while True:
-            with self.lock:
-                if self._stop:
-                    return
-                progress = self._admit()
-                progress |= self._launch()
-                progress |= self._collect()
-                if not progress:
-                    idle = not (self.pending or self.uploading or self.ready or self.inflight or self.downloading)
-                    self.lock.wait(timeout=0.01 if idle else 2e-5)
+        while not self._stop:
+            self._wake.clear()  # a submit after this point wakes the next wait
+            while self.incoming:
+                self.pending.append(self.incoming.popleft())
+            progress = self._admit()
+            progress |= self._launch()
+            progress |= self._collect()
+            if not progress:
+                idle = not (self.pending or self.uploading or self.ready or self.inflight or self.downloading)
+                self._wake.wait(timeout=0.01 if idle else 2e-5)
 
 
 class GpuBackend:
