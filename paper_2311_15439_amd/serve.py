@@ -23,6 +23,7 @@ chunking, back-pressure and failure handling without a GPU.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import itertools
 import threading
 import time
@@ -74,6 +75,7 @@ class Chunk:
     nbytes: int = 0
     up: object = None   # backend handle of the upload
     down: object = None
+    copy: object = None  # future of the result copy into the request
 
 
 class Arena:
@@ -113,7 +115,13 @@ class Arena:
         return sum(s for _, s in self.free)
 
 
+_DONE = concurrent.futures.Future()
+_DONE.set_result(None)
+
+
 class Server:
+    COPY_ASIDE_BYTES = 1 << 20  # results at least this large are copied out on a worker thread
+
     def __init__(self, backend, field_dims: List[int], field_outs: List[int], arena_bytes: int = 1 << 30,
                  chunk_points: int = 1 << 18, batch_points: int = 1 << 21, max_inflight: int = 2):
         self.backend = backend
@@ -131,6 +139,8 @@ class Server:
         self.ready: List[Chunk] = []
         self.inflight: List[tuple] = []                           # (handle, chunks)
         self.downloading: List[Chunk] = []
+        self.finishing: List[Chunk] = []                          # results being copied out
+        self._copier = concurrent.futures.ThreadPoolExecutor(max_workers=2, thread_name_prefix="spx-results")
         self.completed: List[Request] = []
         self._ids = itertools.count()
         self._stop = False
@@ -179,6 +189,7 @@ class Server:
         self._wake.set()
         if self._thread:
             self._thread.join()
+        self._copier.shutdown(wait=True)
 
     def _fail(self, req: Request, msg: str) -> None:
         if not req.done:
@@ -224,7 +235,13 @@ class Server:
     def _launch(self) -> bool:
         still = []
         for c in self.uploading:
-            (self.ready if self.backend.done(c.up) else still).append(c)
+            try:
+                up = self.backend.done(c.up)
+            except Exception as e:  # the upload failed: its request fails, the server keeps going
+                self.arena.release(c.off, c.nbytes)
+                self._fail(c.req, f"upload failed: {e}")
+                continue
+            (self.ready if up else still).append(c)
         self.uploading = still
         if not self.ready or len(self.inflight) >= self.max_inflight:
             return False
@@ -263,17 +280,40 @@ class Server:
         for c in self.downloading:
             if self.backend.done(c.down):
                 if not c.req.done:
-                    c.req.out[c.lo:c.hi] = self.backend.result(c.down)
-                    c.req.chunks_left -= 1
-                    if c.req.chunks_left == 0:
-                        c.req.t_done = time.perf_counter()
-                        c.req._event.set()
-                        self.completed.append(c.req)
-                self.arena.release(c.off, c.nbytes)
+                    dst, src = c.req.out[c.lo:c.hi], self.backend.result(c.down)
+                    if dst.nbytes >= self.COPY_ASIDE_BYTES:
+                        # large results are copied out on a worker; the arena
+                        # range is released once the copy has finished
+                        c.copy = self._copier.submit(np.copyto, dst, src)
+                    else:
+                        np.copyto(dst, src)
+                        c.copy = _DONE
+                    self.finishing.append(c)
+                else:
+                    self.arena.release(c.off, c.nbytes)
                 progress = True
             else:
                 keep.append(c)
         self.downloading = keep
+        keep = []
+        for c in self.finishing:
+            if not c.copy.done():
+                keep.append(c)
+                continue
+            self.arena.release(c.off, c.nbytes)
+            progress = True
+            if c.req.done:
+                continue
+            err = c.copy.exception()
+            if err is not None:
+                self._fail(c.req, f"result copy failed: {err}")
+                continue
+            c.req.chunks_left -= 1
+            if c.req.chunks_left == 0:
+                c.req.t_done = time.perf_counter()
+                c.req._event.set()
+                self.completed.append(c.req)
+        self.finishing = keep
         return progress
 
     def _loop(self) -> None:
@@ -285,7 +325,8 @@ class Server:
             progress |= self._launch()
             progress |= self._collect()
             if not progress:
-                idle = not (self.pending or self.uploading or self.ready or self.inflight or self.downloading)
+                idle = not (self.pending or self.uploading or self.ready or self.inflight or self.downloading
+                            or self.finishing)
                 self._wake.wait(timeout=0.01 if idle else 2e-5)
 
 
@@ -314,6 +355,7 @@ class GpuBackend:
         self.seg_pinned = [torch.empty(n, dtype=torch.uint8, pin_memory=True) for _ in range(self.RING)]
         self.seg_dev = [torch.empty(n, dtype=torch.uint8, device=device) for _ in range(self.RING)]
         self.seg_next = 0
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=4, thread_name_prefix="spx-upload")
 
     def alloc_arena(self, nbytes: int) -> None:
         t = self.torch
@@ -328,6 +370,11 @@ class GpuBackend:
         return e
 
     def upload(self, off: int, pts: np.ndarray):
+        """Stage the points in the pinned mirror and copy them to the arena,
+        on a worker thread (the host copy is the scheduler's largest cost)."""
+        return self.pool.submit(self._upload, off, pts)
+
+    def _upload(self, off: int, pts: np.ndarray):
         n = pts.nbytes
         dst = self.host_in[off:off + n].numpy()
         dst[:] = pts.view(np.uint8).reshape(-1)
@@ -366,6 +413,10 @@ class GpuBackend:
         return (ev, off, shape)
 
     def done(self, h) -> bool:
+        if isinstance(h, concurrent.futures.Future):
+            if not h.done():
+                return False
+            h = h.result()  # re-raises a failed upload
         ev = h[0] if isinstance(h, tuple) else h
         return ev.query()
 
