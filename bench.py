@@ -605,6 +605,41 @@ def time_fused_query(ts, reps=20):
     return {"fused_ms": e[0].elapsed_time(e[1]) / reps, "separate_ms": e[1].elapsed_time(e[2]) / reps}
 
 
+def cpu_encode_rates(S=1 << 15):
+    """The oracle's encoding forward on the host cores (all threads, then
+    one): the plain 2-D configuration in full and the dimension sweep on a
+    sample of S points, simplex and grid (points/s; beside the GPU table
+    above, as the paper reports CPU timings per dimension)."""
+    import oracle
+    from paper_2311_15439_amd import inputs
+    threads = oracle.max_threads()
+    out = {"threads_all": threads, "sample_points": S}
+    cases = [inputs.PLAIN_2D] + [inputs.sweep_workload(n) for n in range(2, 7)]
+    data = []
+    for w in cases:
+        N = w.n_points if w is inputs.PLAIN_2D else S
+        pts = inputs.uniform_points(N, w.n_dims, w.seed_points)
+        tab = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, w.table_f16)
+        res = oracle.level_resolutions(w.n_min, w.growth, w.n_levels)
+        data.append((w, N, pts, tab, res))
+    try:
+        for nt in (threads, 1):
+            oracle.set_threads(nt)
+            w, N, pts, tab, res = data[0]
+            oracle.encode_fwd(oracle.Encoding(w.n_dims, list(res), w.log2_T, w.n_feat), pts[:1024], tab)  # warm-up
+            for w, N, pts, tab, res in data:
+                row = out.setdefault(w.name, {})
+                for cell, cname in ((oracle.SIMPLEX, "simplex"), (oracle.GRID, "grid")):
+                    e = oracle.Encoding(w.n_dims, list(res), w.log2_T, w.n_feat,
+                                        table_dtype=oracle.F16 if w.table_f16 else oracle.F32, cell=cell)
+                    t0 = time.perf_counter()
+                    oracle.encode_fwd(e, pts, tab)
+                    row[f"{cname}_points_per_s_{nt}t"] = N / (time.perf_counter() - t0)
+    finally:
+        oracle.set_threads(threads)
+    return out
+
+
 def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
     """The oracle (as it stands) on a bounded sample of the same step: the
     per-point work on S points, Adam on 1/16 of the tables; scaled to one
@@ -837,10 +872,11 @@ def main():
         print("# serving: training resident fields, then saturation and Poisson loads", file=sys.stderr, flush=True)
         serving = serving_bench()
 
-    cpu = None
+    cpu, cpu_rates = None, None
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, host_tables, weights, batches[0])
+        cpu_rates = cpu_encode_rates()
 
     value = w.n_points / (ms * 1e-3)
     line = {
@@ -865,6 +901,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "avg_ms": kern[dom]["avg_ms"], "bytes_per_launch": kern[dom]["bytes_per_launch"]},
         "cpu_baseline": cpu,
+        "cpu_encode_rates": cpu_rates,
         "kernels": kernels,
         "calls": calls,
         "encode_only": {"simplex": enc_s, "grid": grid["encode_only"] if grid else None},

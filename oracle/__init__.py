@@ -79,6 +79,8 @@ def lib():
             ("orc_mse_grad", None, [C.c_int64, P, P, C.c_double, P]),
             ("orc_encode_input_grad", None, [P, C.c_int64, P, P, P, P, P]),
             ("orc_composite_fwd", None, [C.c_int64, C.c_int, P, P, P]),
+            ("orc_set_threads", None, [C.c_int]),
+            ("orc_max_threads", C.c_int, []),
             ("orc_composite_bwd", None, [C.c_int64, C.c_int, P, P, P, P, P]),
         ]:
             fn = getattr(L, name)
@@ -332,4 +334,13 @@ def composite_bwd(raw, delta, d_rgba, with_mag: bool = False):
     mag = np.zeros((R, S, 4), np.float64) if with_mag else None
     lib().orc_composite_bwd(R, S, _p(a), _p(d), _p(g), _p(out), _p(mag) if with_mag else None)
     return (out, mag) if with_mag else out
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the parallel oracle loops (for timing)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 

@@ -25,6 +25,7 @@
  * closed-form special cases; nothing here is "parity unpinned".
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -749,3 +750,8 @@ void orc_composite_bwd(int64_t R, int S, const float* raw, const float* delta, c
         }
     }
 }
+
+/* Number of OpenMP threads the parallel loops above use (timing only). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
