@@ -20,6 +20,21 @@ struct alignas(F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64) BinRec {
     float v[F];
 };
 
+// Float add into LDS.  On this chip the LDS float-add instruction keeps the
+// LDS busy for about 200 cycles per wave, a 32-bit compare-and-swap for a
+// small fraction of that, so the add is a compare-and-swap loop: one pass
+// unless another lane changed the word in between, in which case the lane
+// retries with the value it saw.
+__device__ __forceinline__ void lds_add(float* p, float v) {
+    uint32_t* q = reinterpret_cast<uint32_t*>(p);
+    uint32_t seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    uint32_t want;
+    do {
+        want = __float_as_uint(__uint_as_float(seen) + v);
+    } while (!__hip_atomic_compare_exchange_strong(q, &seen, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP));
+}
+
 constexpr int kAccBlock = 512;
 constexpr int kAccUnroll = 2;
 
@@ -36,23 +51,23 @@ __device__ __forceinline__ void adam4(const AdamArgs& a, f32x4 g, f32x4& p, f32x
     }
 }
 
-// Adds one record per lane to the LDS accumulator.  A bucket's records are
-// stored in point order, and spatially coherent points (samples along a
-// ray) give runs of records for the same slot; 64 lanes adding to one
-// address serialise in LDS.  So when any lane holds the same slot as the
-// lane before it, the wave first sums each run of equal slots across lanes
-// (a segmented scan) and only the run's last lane adds the sum.  The sums
-// group the same terms in a different order.
+// Adds one value per lane (F floats at acc[slot * F]) to an LDS
+// accumulator.  Spatially coherent points (samples along a ray) put runs of
+// lanes on the same slot, and a compare-and-swap add retries once per lane
+// that got in first.  So when any lane holds the same slot as the lane
+// before it, the wave first sums each run of equal slots across lanes (a
+// segmented scan) and only the run's last lane adds the sum.  The sums group
+// the same terms in a different order.  Every lane of the wave must call it.
 template <int F>
-__device__ __forceinline__ void add_record_wave(float* acc, bool ok, const BinRec<F>& rec) {
+__device__ __forceinline__ void lds_add_wave(float* acc, bool ok, uint32_t slot, const float (&val)[F]) {
     const int lane = threadIdx.x & 63;
-    const uint32_t key = ok ? rec.slot : 0xFFFFFFFFu;
+    const uint32_t key = ok ? slot : 0xFFFFFFFFu;
     const uint32_t prev = __shfl_up(key, 1, 64);
     const bool joins = ok && lane > 0 && prev == key;
     if (__ballot(joins) == 0) {
         if (ok)
 #pragma unroll
-            for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], rec.v[j]);
+            for (int j = 0; j < F; ++j) lds_add(&acc[slot * F + j], val[j]);
         return;
     }
     int start = joins ? 0 : lane;  // first lane of this lane's run
@@ -63,7 +78,7 @@ __device__ __forceinline__ void add_record_wave(float* acc, bool ok, const BinRe
     }
     float v[F];
 #pragma unroll
-    for (int j = 0; j < F; ++j) v[j] = ok ? rec.v[j] : 0.0f;
+    for (int j = 0; j < F; ++j) v[j] = ok ? val[j] : 0.0f;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
 #pragma unroll
@@ -75,7 +90,14 @@ __device__ __forceinline__ void add_record_wave(float* acc, bool ok, const BinRe
     const int next_joins = __shfl_down((int)joins, 1, 64);
     if (ok && (lane == 63 || !next_joins))
 #pragma unroll
-        for (int j = 0; j < F; ++j) atomicAdd(&acc[rec.slot * F + j], v[j]);
+        for (int j = 0; j < F; ++j) lds_add(&acc[slot * F + j], v[j]);
+}
+
+// A bucket's records are stored in point order, so runs of records for one
+// slot come from coherent points.
+template <int F>
+__device__ __forceinline__ void add_record_wave(float* acc, bool ok, const BinRec<F>& rec) {
+    lds_add_wave<F>(acc, ok, rec.slot, rec.v);
 }
 
 constexpr int kAccPre = 8;  // float4 chunks of the slice a thread preloads
@@ -127,7 +149,7 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
 #pragma unroll
             for (int j = 0; j < F; ++j) {
                 const float g = plan.gdense[(size_t)e * F + j];
-                if (g != 0.0f) atomicAdd(&acc[(h & smask) * F + j], g);
+                if (g != 0.0f) lds_add(&acc[(h & smask) * F + j], g);
             }
         }
     }

@@ -398,6 +398,8 @@ __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t
 
 // Privatised coarse levels: each workgroup sums its points' contributions
 // from in-box cells into a dense LDS array, then stores it as its partial.
+// The point loop's bounds are uniform over the workgroup (lanes past the
+// chunk idle) because the wave-level adds need every lane.
 template <class Tag, int D, int F, typename GT>
 __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const float* __restrict__ pts,
                                                                const GT* __restrict__ d_out, LevelArgs lv,
@@ -408,7 +410,9 @@ __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const 
     __syncthreads();
     int64_t lo, hi;
     bin_chunk(N, plan.chunk, lo, hi);
-    for (int64_t pt = lo + threadIdx.x; pt < hi; pt += kBinBlock) {
+    for (int64_t p0 = lo; p0 < hi; p0 += kBinBlock) {
+        const bool in = p0 + threadIdx.x < hi;
+        const int64_t pt = in ? p0 + threadIdx.x : lo;
         float y[D];
         load_point<Tag, D>(pts, pt, lv.Fn, y);
         const GT* __restrict__ grow = d_out + pt * (int64_t)(lv.L * F);
@@ -419,12 +423,28 @@ __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const 
                            [&](const auto& h, const auto& w, int, const auto& cell, const auto& offs) {
                 constexpr int K = sizeof(w) / sizeof(float);
                 int32_t e0, stride[D];
-                if (!dense_cell<D>(plan, l, cell, e0, stride)) return;  // emitted as records instead
+                // cells outside the box are emitted as records instead
+                const bool ok = dense_cell<D>(plan, l, cell, e0, stride) && in;
+                // Lanes in different cells almost never share a vertex at the
+                // same list position.  The run merging costs about as much as
+                // a few retried adds, so it is used when at least 8 lanes share
+                // their cell with the lane before them (a wave-uniform test):
+                // coherent points, not the odd pair of random ones.
+                const uint32_t ck = ok ? (uint32_t)e0 : 0xFFFFFFFFu;
+                const bool coherent =
+                    __popcll(__ballot(ok && (threadIdx.x & 63) > 0 && __shfl_up(ck, 1, 64) == ck)) >= 8;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const int32_t e = dense_vertex<D>(e0, stride, offs[k]);
+                    float v[F];
 #pragma unroll
-                    for (int j = 0; j < F; ++j) atomicAdd(&dacc[e * F + j], w[k] * g[j]);
+                    for (int j = 0; j < F; ++j) v[j] = w[k] * g[j];
+                    const uint32_t e = (uint32_t)dense_vertex<D>(e0, stride, offs[k]);
+                    if (coherent) {
+                        lds_add_wave<F>(dacc, ok, e, v);
+                    } else if (ok) {
+#pragma unroll
+                        for (int j = 0; j < F; ++j) lds_add(&dacc[e * F + j], v[j]);
+                    }
                 }
             });
         }
@@ -464,10 +484,18 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
     trace_end(c.stream);
+    trace_begin(c.stream, "bin_colscan", 2.0 * counts + 4.0 * p.B);
+    bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
+    trace_end(c.stream);
+    trace_begin(c.stream, "bin_scan", 8.0 * p.B + 4.0);
+    bin_scan_kernel<<<1, 1024, 0, c.stream>>>(p.B, totals, p.base);
+    trace_end(c.stream);
     // The privatised coarse levels depend only on the points and the output
     // gradient, and their sums are needed only by the accumulation: they run
-    // on a side stream beside count / scan / scatter (LDS-atomic bound beside
-    // store bound) and are joined before the accumulation.
+    // on a side stream beside the scatter (LDS-atomic bound beside store
+    // bound) and are joined before the accumulation.  They are forked after
+    // the scan: forked earlier, their workgroups hold every CU and the
+    // one-workgroup scan waits for them to drain.
     std::unique_lock<std::mutex> aux_lock;
     AuxStream* aux = nullptr;
     if (p.P > 0) {
@@ -489,12 +517,6 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
             if (e != hipSuccess) return e;
         }
     }
-    trace_begin(c.stream, "bin_colscan", 2.0 * counts + 4.0 * p.B);
-    bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
-    trace_end(c.stream);
-    trace_begin(c.stream, "bin_scan", 8.0 * p.B + 4.0);
-    bin_scan_kernel<<<1, 1024, 0, c.stream>>>(p.B, totals, p.base);
-    trace_end(c.stream);
     trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + recs);
     bool staged = false;
     if constexpr (stage_ppt<V>() >= 1) {
