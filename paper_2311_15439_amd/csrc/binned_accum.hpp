@@ -12,10 +12,12 @@
 
 namespace spx {
 
-// One record per contribution: slot within the bucket and the F values,
-// padded to a power of two so that a record is one aligned store.
+// One record per contribution: slot within the bucket and the F values.
+// F = 1 and F = 2 records are unpadded (8 and 12 bytes: one 64- or 96-bit
+// access, and a wave's run of records is contiguous); wider ones are padded
+// to a power of two.
 template <int F>
-struct alignas(F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64) BinRec {
+struct alignas(F == 1 ? 8 : F == 2 ? 4 : F == 4 ? 32 : 64) BinRec {
     uint32_t slot;
     float v[F];
 };

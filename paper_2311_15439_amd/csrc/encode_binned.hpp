@@ -47,9 +47,10 @@ constexpr int kBinBlock = 256;
 // while that kernel streams the table state.  Only the staged scatter uses it,
 // where a wave's stores form contiguous runs (scattered non-temporal stores
 // would reach HBM as partial lines).
+typedef float f32x3_a4 __attribute__((ext_vector_type(3), aligned(4)));
 template <int F>
 __device__ __forceinline__ void store_rec_nt(BinRec<F>* p, const BinRec<F>& r) {
-    constexpr int W = sizeof(BinRec<F>) / 4;  // 32-bit words, a power of two >= 2
+    constexpr int W = sizeof(BinRec<F>) / 4;  // 32-bit words: 2, 3 or a power of two >= 4
     float w[W];
     w[0] = __builtin_bit_cast(float, r.slot);
 #pragma unroll
@@ -58,6 +59,8 @@ __device__ __forceinline__ void store_rec_nt(BinRec<F>* p, const BinRec<F>& r) {
     for (int j = F + 1; j < W; ++j) w[j] = 0.0f;
     if constexpr (W == 2) {
         __builtin_nontemporal_store(f32x2{w[0], w[1]}, reinterpret_cast<f32x2*>(p));
+    } else if constexpr (W == 3) {
+        __builtin_nontemporal_store(f32x3_a4{w[0], w[1], w[2]}, reinterpret_cast<f32x3_a4*>(p));
     } else {
 #pragma unroll
         for (int c = 0; c < W / 4; ++c)

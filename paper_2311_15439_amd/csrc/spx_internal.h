@@ -91,7 +91,7 @@ inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simp
     b.L = L;
     b.N = N;
     b.V = simplex ? D + 1 : (1 << D);
-    b.rec_bytes = F == 1 ? 8 : F == 2 ? 16 : F == 4 ? 32 : 64;
+    b.rec_bytes = F == 1 ? 8 : F == 2 ? 12 : F == 4 ? 32 : 64;  // sizeof(BinRec<F>)
     const int lf = F == 1 ? 0 : F == 2 ? 1 : F == 4 ? 2 : 3;
     // bucket of 2^s slots: its binary32 accumulator (2^s * F * 4 bytes) is
     // 64 KiB, or 128 KiB when needed to keep at most 16384 buckets per level

@@ -118,7 +118,7 @@ def test_binned_workspace_sizes():
     counters; bigger for more points and more vertices."""
     e2 = spx.Encoding(2, [16] * 16, 22)
     a = spx.spx_encode_bwd_workspace(e2, 1 << 20)
-    assert a >= (1 << 20) * 16 * 3 * 16  # one 16-byte record per (point, level, vertex)
+    assert a >= (1 << 20) * 16 * 3 * 12  # one 12-byte record (F = 2) per (point, level, vertex)
     assert spx.spx_encode_bwd_workspace(e2, 1 << 10) < a
     g3 = spx.Encoding(3, [16] * 16, 19, cell=spx.SPX_GRID)
     s3 = spx.Encoding(3, [16] * 16, 19)
