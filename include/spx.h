@@ -90,8 +90,10 @@ const char* spx_last_error(void);
  * events[2i] / events[2i+1], recorded on its launch stream, and described
  * by names[i] (a static string) and bytes[i] (the bytes the kernel must move
  * by its own definition: inputs read plus outputs written).  Kernels beyond
- * capacity are not recorded.  The caller creates the 2 * capacity events
- * and reads the elapsed times after synchronising.  Pass NULL to stop.
+ * capacity are not recorded.  With `only` set, only kernels of that name are
+ * recorded (the others run without events around them).  The caller creates
+ * the 2 * capacity events and reads the elapsed times after synchronising.
+ * Pass NULL to stop.
  */
 typedef struct {
     hipEvent_t* events;   /* [2 * capacity] */
@@ -99,6 +101,7 @@ typedef struct {
     double* bytes;        /* [capacity] */
     int32_t capacity;
     int32_t count;        /* kernels recorded so far (written by the library) */
+    const char* only;     /* NULL: every kernel; else the one kernel name to record */
 } spx_trace;
 
 spx_status spx_trace_set(spx_trace* trace);

@@ -17,18 +17,22 @@
 namespace spx {
 
 static thread_local spx_trace* g_trace = nullptr;
+static thread_local bool g_trace_open = false;  // the last trace_begin recorded an event
 
 void trace_begin(hipStream_t s, const char* name, double bytes) {
     spx_trace* t = g_trace;
-    if (!t || t->count >= t->capacity) return;
+    g_trace_open = false;
+    if (!t || t->count >= t->capacity || (t->only && strcmp(t->only, name) != 0)) return;
     hipEventRecord(t->events[2 * t->count], s);
     t->names[t->count] = name;
     t->bytes[t->count] = bytes;
+    g_trace_open = true;
 }
 
 void trace_end(hipStream_t s) {
     spx_trace* t = g_trace;
-    if (!t || t->count >= t->capacity) return;
+    if (!t || !g_trace_open) return;
+    g_trace_open = false;
     hipEventRecord(t->events[2 * t->count + 1], s);
     t->count += 1;
 }

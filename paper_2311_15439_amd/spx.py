@@ -49,7 +49,7 @@ class spx_segment(C.Structure):
 
 class spx_trace(C.Structure):
     _fields_ = [("events", C.c_void_p), ("names", C.c_void_p), ("bytes", C.c_void_p), ("capacity", C.c_int32),
-                ("count", C.c_int32)]
+                ("count", C.c_int32), ("only", C.c_char_p)]
 
 
 class spx_mlp(C.Structure):
@@ -470,9 +470,10 @@ def spx_field_query_batched(fields_dev, nfields: int, segs_dev, nseg: int, total
 class Trace:
     """Per-kernel timing of everything the library launches on this thread
     inside ``with Trace(...)``: name, algorithmic bytes and duration (ms)
-    from HIP events on each kernel's launch stream."""
+    from HIP events on each kernel's launch stream.  ``only`` restricts the
+    events to the kernels of one name."""
 
-    def __init__(self, capacity: int = 256):
+    def __init__(self, capacity: int = 256, only: str = None):
         torch = _torch()
         self.capacity = capacity
         self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * capacity)]
@@ -488,6 +489,8 @@ class Trace:
         self.t.names = C.cast(self._names, C.c_void_p)
         self.t.bytes = C.cast(self._bytes, C.c_void_p)
         self.t.capacity = capacity
+        self._only = only.encode() if only else None
+        self.t.only = self._only
 
     def __enter__(self):
         self.t.count = 0
