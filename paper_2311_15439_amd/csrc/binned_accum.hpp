@@ -37,7 +37,7 @@ __device__ __forceinline__ void lds_add(float* p, float v) {
                                                    __HIP_MEMORY_SCOPE_WORKGROUP));
 }
 
-constexpr int kAccBlock = 512;
+constexpr int kAccBlock = 1024;  // one workgroup per CU (128 KiB accumulator)
 constexpr int kAccUnroll = 2;
 
 // Adam update of four parameters with their summed gradients (the same

@@ -94,9 +94,11 @@ inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simp
     b.rec_bytes = F == 1 ? 8 : F == 2 ? 12 : F == 4 ? 32 : 64;  // sizeof(BinRec<F>)
     const int lf = F == 1 ? 0 : F == 2 ? 1 : F == 4 ? 2 : 3;
     // bucket of 2^s slots: its binary32 accumulator (2^s * F * 4 bytes) is
-    // 64 KiB, or 128 KiB when needed to keep at most 16384 buckets per level
-    int s = 14 - lf;
-    if (log2T - s > 14) s = 15 - lf;
+    // 128 KiB, one accumulation workgroup per CU.  Half the size would let two
+    // share a CU, but the scatter's per-bucket runs of records would be half
+    // as long, and its record stores are bound by those runs.  At most 16384
+    // buckets per level for T <= 2^26.
+    int s = 15 - lf;
     if (s > log2T) s = log2T;
     b.s_log2 = s;
     b.bpl = 1 << (log2T - s);
