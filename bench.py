@@ -533,7 +533,8 @@ def equal_accuracy(w, host_tables, weights, d_out, steps=2000, n_train=6):
         out[name] = {"psnr_db": 10.0 * np.log10(peak * peak / mse), "mse": mse}
         del ts
         torch.cuda.empty_cache()
-    out["simplex_minus_grid_db"] = out["simplex_equal_memory"]["psnr_db"] - out["grid"]["psnr_db"]
+    out["simplex_minus_grid_db"] = out["simplex"]["psnr_db"] - out["grid"]["psnr_db"]
+    out["simplex_equal_memory_minus_grid_db"] = out["simplex_equal_memory"]["psnr_db"] - out["grid"]["psnr_db"]
     return out
 
 
