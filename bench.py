@@ -17,6 +17,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -886,6 +887,10 @@ def main():
     serving = None
     if not args.no_serving:
         print("# serving: training resident fields, then saturation and Poisson loads", file=sys.stderr, flush=True)
+        # the serving scheduler is host-bound: start it without the earlier sections' garbage and
+        # cached allocations
+        gc.collect()
+        torch.cuda.empty_cache()
         serving = serving_bench()
 
     cpu, cpu_rates = None, None
