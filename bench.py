@@ -58,11 +58,12 @@ def _counter_rows(path):
     return out
 
 
-def write_traffic(fetch_csv, write_csv):
+def write_traffic(fetch_csv, write_csv, workload):
     """HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
-    counter runs, each scaled by what the counter reads for the calibration
-    copy of known size (the last cast kernel dispatch)."""
-    res = {"sources_sha256": _sources_digest(), "copy_elems": COPY_ELEMS, "kernels": {}}
+    counter runs of `--pmc-pass` on `workload`, each scaled by what the counter
+    reads for the calibration copy of known size (the last cast kernel
+    dispatch)."""
+    res = {"sources_sha256": _sources_digest(), "workload": workload, "copy_elems": COPY_ELEMS, "kernels": {}}
     known = {"FETCH_SIZE": COPY_ELEMS * 4 / 1024.0, "WRITE_SIZE": COPY_ELEMS * 2 / 1024.0}
     rows = {"FETCH_SIZE": _counter_rows(fetch_csv), "WRITE_SIZE": _counter_rows(write_csv)}
     factor = {}
@@ -83,15 +84,17 @@ def write_traffic(fetch_csv, write_csv):
     print(json.dumps(res))
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch measured by the counter runs, or None if there is
-    no measurement for this kernel or its sources changed since it was taken."""
+    no measurement for this kernel on this workload or its sources changed
+    since it was taken."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
             t = json.load(fh)
     except OSError:
         return None
-    if t.get("sources_sha256") != _sources_digest() or kernel not in t.get("kernels", {}):
+    if (t.get("sources_sha256") != _sources_digest() or t.get("workload") != workload
+            or kernel not in t.get("kernels", {})):
         return None
     return t["kernels"][kernel]["bytes"]
 
@@ -800,10 +803,11 @@ def main():
                     help="run two training steps and a binary32->binary16 copy of 2^26 elements, then exit "
                          "(the program profiled by the rocprofv3 --pmc traffic runs)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn the counter CSVs of the two --pmc runs into " + TRAFFIC_FILE + " and exit")
+                    help="turn the counter CSVs of the two --pmc runs (of --pmc-pass on --workload) into "
+                         + TRAFFIC_FILE + " and exit")
     args = ap.parse_args()
     if args.write_traffic:
-        write_traffic(*args.write_traffic)
+        write_traffic(*args.write_traffic, _workload(args.workload).name)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -919,7 +923,7 @@ def main():
         "config": {"workload": w.name + f", {w.n_points} points/step, MLP {w.n_levels * w.n_feat}-64-64-{d_out}",
                    "levels": res, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, w.name),
                      "avg_ms": kern[dom]["timed_avg_ms"], "bytes_per_launch": kern[dom]["timed_bytes_per_launch"]},
         "cpu_baseline": cpu,
         "cpu_encode_rates": cpu_rates,
