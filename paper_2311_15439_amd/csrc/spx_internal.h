@@ -104,11 +104,12 @@ inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simp
     b.bpl = 1 << (log2T - s);
     b.ok = b.bpl <= 16384 && N >= 0;
     // levels per group: at most 16384 buckets, fewer than 2^31 records, and
-    // at most 1 GiB of records (only the per-point load repeats per group)
+    // at most 2 GiB of records (the count, scan, scatter and accumulation
+    // passes repeat per group, so fewer groups are faster; 2 GiB of 288 GB)
     int lpg = 16384 / b.bpl;
     if (lpg > L) lpg = L;
     const double per_level = (double)N * b.V;
-    while (lpg > 1 && (per_level * lpg >= 2147483647.0 || per_level * lpg * b.rec_bytes > 1073741824.0)) --lpg;
+    while (lpg > 1 && (per_level * lpg >= 2147483647.0 || per_level * lpg * b.rec_bytes > 2147483648.0)) --lpg;
     if (per_level * lpg >= 2147483647.0) b.ok = false;
     if (lpg < 1) { lpg = 1; b.ok = false; }
     b.lpg = lpg;

@@ -177,7 +177,7 @@ BWD_CASES = [
 
 
 BWD_CASES += [
-    (6, [3, 5, 9, 12] * 4, 14, 2, False, spx.SPX_GRID),   # 64 vertices: the binned path runs two level groups
+    (6, [3, 5, 9, 12] * 4, 14, 2, False, spx.SPX_GRID),   # 2^18 pts x 64 vertices: two level groups
     (3, [16, 64], 24, 8, True, spx.SPX_SIMPLEX),          # 2^24-entry tables, 8 features
 ]
 
@@ -187,7 +187,7 @@ BWD_CASES += [
 def test_bwd_parity(case, binned):
     n, res, log2_T, F, dout_f16, cell = case
     g, o = _enc_pair(n, res, log2_T, F, False, cell)
-    N = (1 << 17) + 3 if n == 6 and cell == spx.SPX_GRID else 6001
+    N = (1 << 18) + 3 if n == 6 and cell == spx.SPX_GRID else 6001
     # uniform points plus edge points, some outside the unit cube (their
     # coarse cells fall outside the binned path's dense boxes)
     pts = np.concatenate([inputs.uniform_points(N, n, 500 + n),
@@ -308,10 +308,10 @@ def test_binned_equals_atomic_on_the_image_workload():
 FUSED_CASES = [
     (3, [4, 16, 64, 200], 13, 20001, spx.SPX_SIMPLEX),
     (3, [4, 16, 64, 200], 13, 20001, spx.SPX_GRID),
-    # 2^17 points x 64 corners x 16 levels: 134 MB of records per level, so
-    # the binned path runs three level groups (at most 1 GiB of records
-    # each) and applies the Adam step group by group
-    (6, [int(4 * 1.25 ** l) for l in range(16)], 12, (1 << 17) + 3, spx.SPX_GRID),
+    # 2^18 points x 64 corners x 16 levels: 201 MB of records per level, so
+    # the binned path runs two level groups (at most 2 GiB of records each)
+    # and applies the Adam step group by group
+    (6, [int(4 * 1.25 ** l) for l in range(16)], 12, (1 << 18) + 3, spx.SPX_GRID),
 ]
 
 
