@@ -19,8 +19,11 @@ LIB = os.path.join(HERE, "libspx.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPX_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "encode_simplex.hip", "encode_grid.hip", "mlp.hip", "optim.hip", "field_query.hip",
-           "composite.hip"]
+SOURCES = ["api.hip", "mlp.hip", "optim.hip", "field_query.hip", "composite.hip"]
+# encode_unit.hip is compiled once per (cell, dimension, features): (object name, defines)
+UNITS = [(f"encode_{'grid' if g else 'simplex'}_d{d}_f{f}",
+          [f"-DSPX_UNIT_GRID={g}", f"-DSPX_UNIT_DIM={d}", f"-DSPX_UNIT_F={f}"])
+         for g in (1, 0) for d in (6, 5, 4, 3, 2, 1) for f in (2, 8, 4, 1)]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -30,8 +33,7 @@ COMMON = [
 ]
 # The encoding's index path must follow the IEEE operation order exactly.
 PER_FILE = {
-    "encode_simplex.hip": ["-ffp-contract=off"],
-    "encode_grid.hip": ["-ffp-contract=off"],
+    "encode_unit.hip": ["-ffp-contract=off"],
     # the fused adjoint + Adam (in the encode units) and the standalone Adam
     # perform the same binary32 operation sequence
     "optim.hip": ["-ffp-contract=off"],
@@ -39,9 +41,10 @@ PER_FILE = {
 }
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = ["hipcc", *COMMON, *PER_FILE.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, name, defines = job
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = ["hipcc", *COMMON, *PER_FILE.get(src, []), *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -50,8 +53,10 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    # the slowest units (grid, high dimensions) first
+    jobs = [("encode_unit.hip", name, d) for name, d in UNITS] + [(s, s.replace(".hip", ""), []) for s in SOURCES]
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

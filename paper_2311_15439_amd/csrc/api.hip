@@ -159,7 +159,7 @@ spx::BinLayout layout_for(const spx_encoding* e, int64_t N) {
 }
 
 hipError_t run(const spx_encoding* e, const spx::EncodeCall& c) {
-    return e->cell == SPX_GRID ? spx::encode_grid(c) : spx::encode_simplex(c);
+    return e->cell == SPX_GRID ? spx::encode_cell<true>(c) : spx::encode_cell<false>(c);
 }
 
 spx_status check_points(int64_t N, const float* pts) {
@@ -368,6 +368,7 @@ spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts
     if ((idx && !aligned(idx, 4)) || (w && !aligned(w, 4))) return fail(SPX_EALIGN, "idx/w not 4-byte aligned");
     spx::EncodeCall c = base_call(enc, N, pts, stream);
     c.op = spx::EncodeOp::Debug;
+    c.F = 2;  // slots and weights do not depend on the feature count
     c.idx = idx;
     c.w = w;
     return from_hip(run(enc, c), "spx_encode_debug launch");

@@ -66,61 +66,38 @@ hipError_t input_grad_dispatch_types(const EncodeCall& c) {
     return hipGetLastError();
 }
 
-template <class Tag, int D>
-hipError_t dispatch_F(const EncodeCall& c) {
-    if (c.op == EncodeOp::AdjointBinned) {
-        switch (c.F) {
-            case 1: return binned_adjoint<Tag, D, 1>(c);
-            case 2: return binned_adjoint<Tag, D, 2>(c);
-            case 4: return binned_adjoint<Tag, D, 4>(c);
-            case 8: return binned_adjoint<Tag, D, 8>(c);
-            default: return hipErrorInvalidValue;
-        }
+template <class Tag, int D, int F>
+hipError_t dispatch_op(const EncodeCall& c) {
+    switch (c.op) {
+        case EncodeOp::AdjointBinned: return binned_adjoint<Tag, D, F>(c);
+        case EncodeOp::InputGrad: return input_grad_dispatch_types<Tag, D, F>(c);
+        case EncodeOp::Forward: return fwd_dispatch_types<Tag, D, F>(c);
+        case EncodeOp::Adjoint: return bwd_dispatch_types<Tag, D, F>(c);
+        case EncodeOp::Twin:
+            if constexpr (F == 2) {
+                if (!c.table_f16 || !c.out_f16) return hipErrorInvalidValue;
+                trace_begin(c.stream, "encode_twin",
+                            (4.0 * D + (double)c.lv.L * 2 * (vertices<Tag, D>() * 2 + 2)) * (double)c.N);
+                encode_twin_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(
+                    c.N, c.pts, (const f16*)c.tables, (f16*)c.out, c.lv);
+                trace_end(c.stream);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;
+            }
+        case EncodeOp::Debug:
+            // slots and weights do not depend on F: one instantiation serves all
+            if constexpr (F == 2) {
+                trace_begin(c.stream, "encode_debug", (4.0 * D + 8.0 * c.lv.L * vertices<Tag, D>()) * (double)c.N);
+                encode_debug_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, c.idx, c.w,
+                                                                                              c.lv);
+                trace_end(c.stream);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;  // the caller routes the debug view through F = 2
+            }
     }
-    if (c.op == EncodeOp::InputGrad) {
-        switch (c.F) {
-            case 1: return input_grad_dispatch_types<Tag, D, 1>(c);
-            case 2: return input_grad_dispatch_types<Tag, D, 2>(c);
-            case 4: return input_grad_dispatch_types<Tag, D, 4>(c);
-            case 8: return input_grad_dispatch_types<Tag, D, 8>(c);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    if (c.op == EncodeOp::Twin) {
-        if (c.F != 2 || !c.table_f16 || !c.out_f16) return hipErrorInvalidValue;
-        trace_begin(c.stream, "encode_twin", (4.0 * D + (double)c.lv.L * 2 * (vertices<Tag, D>() * 2 + 2)) * (double)c.N);
-        encode_twin_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables,
-                                                                                     (f16*)c.out, c.lv);
-        trace_end(c.stream);
-        return hipGetLastError();
-    }
-    if (c.op == EncodeOp::Debug) {
-        trace_begin(c.stream, "encode_debug", (4.0 * D + 8.0 * c.lv.L * vertices<Tag, D>()) * (double)c.N);
-        encode_debug_kernel<Tag, D><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, c.idx, c.w, c.lv);
-        trace_end(c.stream);
-        return hipGetLastError();
-    }
-    const bool fwd = c.op == EncodeOp::Forward;
-    switch (c.F) {
-        case 1: return fwd ? fwd_dispatch_types<Tag, D, 1>(c) : bwd_dispatch_types<Tag, D, 1>(c);
-        case 2: return fwd ? fwd_dispatch_types<Tag, D, 2>(c) : bwd_dispatch_types<Tag, D, 2>(c);
-        case 4: return fwd ? fwd_dispatch_types<Tag, D, 4>(c) : bwd_dispatch_types<Tag, D, 4>(c);
-        case 8: return fwd ? fwd_dispatch_types<Tag, D, 8>(c) : bwd_dispatch_types<Tag, D, 8>(c);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <class Tag>
-hipError_t dispatch_D(const EncodeCall& c) {
-    switch (c.D) {
-        case 1: return dispatch_F<Tag, 1>(c);
-        case 2: return dispatch_F<Tag, 2>(c);
-        case 3: return dispatch_F<Tag, 3>(c);
-        case 4: return dispatch_F<Tag, 4>(c);
-        case 5: return dispatch_F<Tag, 5>(c);
-        case 6: return dispatch_F<Tag, 6>(c);
-        default: return hipErrorInvalidValue;
-    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace spx

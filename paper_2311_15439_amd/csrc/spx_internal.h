@@ -190,8 +190,44 @@ struct EncodeCall {
     hipStream_t stream;
 };
 
-hipError_t encode_simplex(const EncodeCall& c);
-hipError_t encode_grid(const EncodeCall& c);
+// Kernels of one (cell, dimension, feature count), one translation unit
+// each (encode_unit.hip); encode_cell() picks the triple.
+template <bool Grid, int D, int F>
+hipError_t encode_unit(const EncodeCall& c);
+#define SPX_DECLARE_UNIT(G, D) \
+    template <> hipError_t encode_unit<G, D, 1>(const EncodeCall& c); \
+    template <> hipError_t encode_unit<G, D, 2>(const EncodeCall& c); \
+    template <> hipError_t encode_unit<G, D, 4>(const EncodeCall& c); \
+    template <> hipError_t encode_unit<G, D, 8>(const EncodeCall& c);
+SPX_DECLARE_UNIT(false, 1) SPX_DECLARE_UNIT(false, 2) SPX_DECLARE_UNIT(false, 3)
+SPX_DECLARE_UNIT(false, 4) SPX_DECLARE_UNIT(false, 5) SPX_DECLARE_UNIT(false, 6)
+SPX_DECLARE_UNIT(true, 1) SPX_DECLARE_UNIT(true, 2) SPX_DECLARE_UNIT(true, 3)
+SPX_DECLARE_UNIT(true, 4) SPX_DECLARE_UNIT(true, 5) SPX_DECLARE_UNIT(true, 6)
+#undef SPX_DECLARE_UNIT
+
+template <bool Grid, int D>
+inline hipError_t encode_dim(const EncodeCall& c) {
+    switch (c.F) {
+        case 1: return encode_unit<Grid, D, 1>(c);
+        case 2: return encode_unit<Grid, D, 2>(c);
+        case 4: return encode_unit<Grid, D, 4>(c);
+        case 8: return encode_unit<Grid, D, 8>(c);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool Grid>
+inline hipError_t encode_cell(const EncodeCall& c) {
+    switch (c.D) {
+        case 1: return encode_dim<Grid, 1>(c);
+        case 2: return encode_dim<Grid, 2>(c);
+        case 3: return encode_dim<Grid, 3>(c);
+        case 4: return encode_dim<Grid, 4>(c);
+        case 5: return encode_dim<Grid, 5>(c);
+        case 6: return encode_dim<Grid, 6>(c);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 // MLP and elementwise kernels.
 struct MlpCall {
