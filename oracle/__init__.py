@@ -38,6 +38,28 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_timing(dst: str) -> str:
+    """Compile the same source for timing on the host that runs it:
+    ``-O3 -march=native`` (same operation order, no contraction), into
+    ``dst``.  The parity build above stays as it is."""
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-o", dst, _SRC, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return dst
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (for example
+    the timing build) from now on."""
+    global _LIB, _lib
+    _LIB, _lib = path, None
+    lib()
+
+
+def library_path() -> str:
+    return _LIB
+
+
 class _Enc(C.Structure):
     _fields_ = [("n_dims", C.c_int), ("n_levels", C.c_int), ("log2_T", C.c_int),
                 ("n_feat", C.c_int), ("table_dtype", C.c_int), ("cell", C.c_int),
@@ -71,8 +93,8 @@ def lib():
             ("orc_encode_fwd_absmag", None, [P, C.c_int64, P, P, P]),
             ("orc_encode_bwd", None, [P, C.c_int64, P, P, P, P, P]),
             ("orc_mlp_fwd", None, [C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P]),
-            ("orc_mlp_bwd", None, [C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P, P, P,
-                                   P]),
+            ("orc_mlp_bwd", None, [C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P, P, C.c_int, P, P, P,
+                                   P, P, P, P, P, P]),
             ("orc_adam_step", None, [C.c_int64, P, P, P, P, C.c_double, C.c_double, C.c_double,
                                      C.c_double, C.c_int64, P]),
             ("orc_cast_f32_f16", None, [C.c_int64, P, P]),
@@ -242,7 +264,8 @@ def _h(a):
 
 def mlp_fwd(x, W1, W2, W3, with_absmag: bool = False):
     """x [N, d_in] binary16; W1 [H, d_in], W2 [H, H], W3 [d_out, H] binary16.
-    Returns the output [N, d_out] in binary64 (and the magnitude bound)."""
+    Returns the output [N, d_out] in binary64 (and its magnitude with the
+    ReLU pattern applied)."""
     x, W1, W2, W3 = _h(x), _h(W1), _h(W2), _h(W3)
     N, d_in = x.shape
     H, d_out = W1.shape[0], W3.shape[0]
@@ -253,21 +276,30 @@ def mlp_fwd(x, W1, W2, W3, with_absmag: bool = False):
     return (out, mag) if with_absmag else out
 
 
-def mlp_bwd(x, W1, W2, W3, d_y):
-    """Returns dict(d_x, dW1, dW2, dW3, margin) in binary64."""
+MLP_BF16, MLP_EXACT = 0, 1
+
+
+def mlp_bwd(x, W1, W2, W3, d_y, mode: int = MLP_BF16, with_mag: bool = False):
+    """Returns dict(d_x, dW1, dW2, dW3, margin) in binary64 (plus mag_d_x,
+    mag_dW1..3 with ``with_mag``).  mode MLP_BF16: operands rounded to
+    bfloat16 where the kernel feeds its matrix unit; MLP_EXACT: the
+    network's derivative with no rounding beyond the stored activations."""
     x, W1, W2, W3 = _h(x), _h(W1), _h(W2), _h(W3)
     N, d_in = x.shape
     H, d_out = W1.shape[0], W3.shape[0]
     dy = np.ascontiguousarray(d_y, np.float32)
     assert dy.shape == (N, d_out)
-    d_x = np.zeros((N, d_in), np.float64)
-    dW1 = np.zeros((H, d_in), np.float64)
-    dW2 = np.zeros((H, H), np.float64)
-    dW3 = np.zeros((d_out, H), np.float64)
-    margin = np.zeros(N, np.float64)
-    lib().orc_mlp_bwd(N, d_in, H, d_out, _p(x), _p(W1), _p(W2), _p(W3), _p(dy), _p(d_x),
-                      _p(dW1), _p(dW2), _p(dW3), _p(margin))
-    return dict(d_x=d_x, dW1=dW1, dW2=dW2, dW3=dW3, margin=margin)
+    out = dict(d_x=np.zeros((N, d_in), np.float64), dW1=np.zeros((H, d_in), np.float64),
+               dW2=np.zeros((H, H), np.float64), dW3=np.zeros((d_out, H), np.float64),
+               margin=np.zeros(N, np.float64))
+    mags = [None] * 4
+    if with_mag:
+        for k in ("d_x", "dW1", "dW2", "dW3"):
+            out["mag_" + k] = np.zeros_like(out[k])
+        mags = [out["mag_d_x"], out["mag_dW1"], out["mag_dW2"], out["mag_dW3"]]
+    lib().orc_mlp_bwd(N, d_in, H, d_out, _p(x), _p(W1), _p(W2), _p(W3), _p(dy), int(mode), _p(out["d_x"]),
+                      _p(out["dW1"]), _p(out["dW2"]), _p(out["dW3"]), _p(out["margin"]), *[_p(m) for m in mags])
+    return out
 
 
 # --- optimizer -------------------------------------------------------------------

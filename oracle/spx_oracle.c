@@ -443,7 +443,10 @@ void orc_encode_bwd(const orc_encoding* e, int64_t N, const float* pts, const do
  * grid), so d p_i / d x_m = sigma (delta_im + F_n) resp. sigma delta_im.
  * On a face the one-sided derivative of the simplex the tie rule picks is
  * returned.  d_out: [N, L*F] binary64; d_pts [N, n] binary64 (overwritten);
- * mag (optional) [N, n]: the same sums over absolute values of the terms.
+ * mag (optional) [N, n]: the same sums over absolute values of the terms
+ * (a walk step's term is its row difference times d_out; a grid term is
+ * c * t * d_out), chained through the skew with the same non-negative
+ * factors.
  */
 void orc_encode_input_grad(const orc_encoding* e, int64_t N, const float* pts, const void* tables,
                            const double* d_out, double* d_pts, double* mag) {
@@ -490,7 +493,7 @@ void orc_encode_input_grad(const orc_encoding* e, int64_t N, const float* pts, c
                         if (verts[k + 1][i] != verts[k][i]) axis = i;
                     for (int j = 0; j < F; ++j) {
                         g[axis] += (t[k + 1][j] - t[k][j]) * d[j];
-                        a[axis] += (fabs(t[k + 1][j]) + fabs(t[k][j])) * fabs(d[j]);
+                        a[axis] += fabs((t[k + 1][j] - t[k][j]) * d[j]);
                     }
                 }
             }
@@ -523,9 +526,13 @@ void orc_encode_input_grad(const orc_encoding* e, int64_t N, const float* pts, c
 
 static double f16r(double v) { return orc_f16_to_f64(orc_f64_to_f16(v)); }
 
-/* out [N, d_out] binary64.  If absmag != NULL it receives the same forward
- * pass over |W| and |x| without the ReLU (an upper bound on every partial
- * sum's size, used for error statements). */
+/* out [N, d_out] binary64.  If absmag != NULL it receives the forward
+ * pass's magnitude with the ReLU pattern applied: per layer the sum of
+ * |w| times the previous layer's magnitude over the units that are active
+ * (positive pre-activation), starting from |x|.  It bounds the size of
+ * every partial sum on a path to the output through active units, which
+ * is where a rounding of a stored activation can travel; with
+ * non-negative weights and inputs it equals the output itself. */
 void orc_mlp_fwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const uint16_t* W1,
                  const uint16_t* W2, const uint16_t* W3, double* out, double* absmag) {
 #pragma omp parallel for schedule(static)
@@ -540,7 +547,7 @@ void orc_mlp_fwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const
                 sa += fabs(w) * fabs(xin[i]);
             }
             h1[o] = f16r(s > 0.0 ? s : 0.0);
-            a1[o] = sa;
+            a1[o] = s > 0.0 ? sa : 0.0;
         }
         for (int o = 0; o < H; ++o) {
             double s = 0.0, sa = 0.0;
@@ -550,7 +557,7 @@ void orc_mlp_fwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const
                 sa += fabs(w) * a1[i];
             }
             h2[o] = f16r(s > 0.0 ? s : 0.0);
-            a2[o] = sa;
+            a2[o] = s > 0.0 ? sa : 0.0;
         }
         for (int o = 0; o < d_out; ++o) {
             double s = 0.0, sa = 0.0;
@@ -566,26 +573,46 @@ void orc_mlp_fwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const
 }
 
 /*
- * Backward pass of the network.  The forward pass is recomputed as above.
- * Gradient operands are rounded to bfloat16 where the kernel feeds them to
- * its matrix unit: the incoming output gradient, the weights in the
- * transposed products, the activations in the weight-gradient products, and
- * each masked hidden gradient.  The ReLU mask is taken on the stored
- * (binary16) activation.
+ * Backward pass of the network.  The forward pass is recomputed as above
+ * (input and hidden activations rounded to binary16 where the forward
+ * stores them).  Two modes:
+ *   ORC_MLP_BF16 (0): gradient operands are rounded to bfloat16 where the
+ *     kernel feeds them to its matrix unit: the incoming output gradient,
+ *     the weights in the transposed products, the activations in the
+ *     weight-gradient products, and each masked hidden gradient.
+ *   ORC_MLP_EXACT (1): the network's own derivative in binary64, with no
+ *     rounding beyond the binary16 storage of the forward's activations.
+ * The ReLU mask is taken on the stored (binary16) activation.
  *   d_y   [N, d_out] binary32 (gradient of the loss w.r.t. the output)
  *   d_x   [N, d_in] binary64 (written)
  *   dW1 [H, d_in], dW2 [H, H], dW3 [d_out, H] binary64 (written)
  *   margin [N] (optional): smallest |pre-activation| of the point, so a test
  *   can tell which points sit on a ReLU kink.
+ *   mag_dx, mag_dW1..3 (optional, shapes as d_x, dW1..3): the same
+ *   products over absolute values of the operands the mode uses, with the
+ *   ReLU mask applied, the hidden gradients' magnitudes propagated
+ *   unrounded; with non-negative weights, inputs and output gradient they
+ *   equal the exact-mode results.
  */
+enum { ORC_MLP_BF16 = 0, ORC_MLP_EXACT = 1 };
+
 void orc_mlp_bwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const uint16_t* W1,
-                 const uint16_t* W2, const uint16_t* W3, const float* d_y, double* d_x, double* dW1,
-                 double* dW2, double* dW3, double* margin) {
+                 const uint16_t* W2, const uint16_t* W3, const float* d_y, int mode, double* d_x, double* dW1,
+                 double* dW2, double* dW3, double* margin, double* mag_dx, double* mag_dW1, double* mag_dW2,
+                 double* mag_dW3) {
+    /* an operand as the mode feeds it to a product */
+#define OP(v) (mode == ORC_MLP_BF16 ? orc_round_bf16(v) : (v))
+    const int with_mag = mag_dx && mag_dW1 && mag_dW2 && mag_dW3;
     memset(dW1, 0, sizeof(double) * H * d_in);
     memset(dW2, 0, sizeof(double) * H * H);
     memset(dW3, 0, sizeof(double) * d_out * H);
+    if (with_mag) {
+        memset(mag_dW1, 0, sizeof(double) * H * d_in);
+        memset(mag_dW2, 0, sizeof(double) * H * H);
+        memset(mag_dW3, 0, sizeof(double) * d_out * H);
+    }
     for (int64_t pt = 0; pt < N; ++pt) {
-        double xin[256], h1[256], h2[256], dy[256], dh2[256], dh1[256];
+        double xin[256], h1[256], h2[256], dy[256], dh2[256], dh1[256], mh2[256], mh1[256];
         double mg = INFINITY;
         for (int i = 0; i < d_in; ++i) xin[i] = orc_f16_to_f64(x[pt * d_in + i]);
         for (int o = 0; o < H; ++o) {
@@ -601,32 +628,57 @@ void orc_mlp_bwd(int64_t N, int d_in, int H, int d_out, const uint16_t* x, const
             if (fabs(s) < mg) mg = fabs(s);
         }
         if (margin) margin[pt] = mg;
-        for (int o = 0; o < d_out; ++o) dy[o] = orc_round_bf16((double)d_y[pt * d_out + o]);
+        for (int o = 0; o < d_out; ++o) dy[o] = OP((double)d_y[pt * d_out + o]);
         /* layer 3: dW3 += dy h2^T ; dh2 = W3^T dy, masked */
         for (int o = 0; o < d_out; ++o)
-            for (int i = 0; i < H; ++i) dW3[o * H + i] += dy[o] * orc_round_bf16(h2[i]);
+            for (int i = 0; i < H; ++i) {
+                dW3[o * H + i] += dy[o] * OP(h2[i]);
+                if (with_mag) mag_dW3[o * H + i] += fabs(dy[o]) * fabs(OP(h2[i]));
+            }
         for (int i = 0; i < H; ++i) {
-            double s = 0.0;
-            for (int o = 0; o < d_out; ++o) s += orc_round_bf16(orc_f16_to_f64(W3[o * H + i])) * dy[o];
-            dh2[i] = orc_round_bf16(h2[i] > 0.0 ? s : 0.0);
+            double s = 0.0, m = 0.0;
+            for (int o = 0; o < d_out; ++o) {
+                const double w = OP(orc_f16_to_f64(W3[o * H + i]));
+                s += w * dy[o];
+                m += fabs(w) * fabs(dy[o]);
+            }
+            dh2[i] = OP(h2[i] > 0.0 ? s : 0.0);
+            mh2[i] = h2[i] > 0.0 ? m : 0.0;
         }
         /* layer 2 */
         for (int o = 0; o < H; ++o)
-            for (int i = 0; i < H; ++i) dW2[o * H + i] += dh2[o] * orc_round_bf16(h1[i]);
+            for (int i = 0; i < H; ++i) {
+                dW2[o * H + i] += dh2[o] * OP(h1[i]);
+                if (with_mag) mag_dW2[o * H + i] += mh2[o] * fabs(OP(h1[i]));
+            }
         for (int i = 0; i < H; ++i) {
-            double s = 0.0;
-            for (int o = 0; o < H; ++o) s += orc_round_bf16(orc_f16_to_f64(W2[o * H + i])) * dh2[o];
-            dh1[i] = orc_round_bf16(h1[i] > 0.0 ? s : 0.0);
+            double s = 0.0, m = 0.0;
+            for (int o = 0; o < H; ++o) {
+                const double w = OP(orc_f16_to_f64(W2[o * H + i]));
+                s += w * dh2[o];
+                m += fabs(w) * mh2[o];
+            }
+            dh1[i] = OP(h1[i] > 0.0 ? s : 0.0);
+            mh1[i] = h1[i] > 0.0 ? m : 0.0;
         }
         /* layer 1 */
         for (int o = 0; o < H; ++o)
-            for (int i = 0; i < d_in; ++i) dW1[o * d_in + i] += dh1[o] * orc_round_bf16(xin[i]);
+            for (int i = 0; i < d_in; ++i) {
+                dW1[o * d_in + i] += dh1[o] * OP(xin[i]);
+                if (with_mag) mag_dW1[o * d_in + i] += mh1[o] * fabs(OP(xin[i]));
+            }
         for (int i = 0; i < d_in; ++i) {
-            double s = 0.0;
-            for (int o = 0; o < H; ++o) s += orc_round_bf16(orc_f16_to_f64(W1[o * d_in + i])) * dh1[o];
+            double s = 0.0, m = 0.0;
+            for (int o = 0; o < H; ++o) {
+                const double w = OP(orc_f16_to_f64(W1[o * d_in + i]));
+                s += w * dh1[o];
+                m += fabs(w) * mh1[o];
+            }
             d_x[pt * d_in + i] = s;
+            if (with_mag) mag_dx[pt * d_in + i] = m;
         }
     }
+#undef OP
 }
 
 /* ------------------------------------------------------------------------ */

@@ -28,9 +28,9 @@ MUTANTS = {
     "grid weight": ("w *= bit ? (double)f[i] : 1.0 - (double)f[i];",
                     "w *= bit ? 1.0 - (double)f[i] : (double)f[i];"),
     "mlp transposed": ("s += w * h1[i];", "s += orc_f16_to_f64(W2[i * H + o]) * h1[i];"),
-    "mlp relu dropped": ("h2[o] = f16r(s > 0.0 ? s : 0.0);\n            a2[o] = sa;",
-                         "h2[o] = f16r(s);\n            a2[o] = sa;"),
-    "mlp bwd mask": ("dh1[i] = orc_round_bf16(h1[i] > 0.0 ? s : 0.0);", "dh1[i] = orc_round_bf16(s);"),
+    "mlp relu dropped": ("h2[o] = f16r(s > 0.0 ? s : 0.0);\n            a2[o] = s > 0.0 ? sa : 0.0;",
+                         "h2[o] = f16r(s);\n            a2[o] = s > 0.0 ? sa : 0.0;"),
+    "mlp bwd mask": ("dh1[i] = OP(h1[i] > 0.0 ? s : 0.0);", "dh1[i] = OP(s);"),
     "f16 rounding": ("double q = nearbyint(ldexp(a, 10 - e));", "double q = floor(ldexp(a, 10 - e));"),
     "mse sign": ("d_y[i] = scale * ((double)y[i] - (double)target[i]);",
                  "d_y[i] = scale * ((double)target[i] - (double)y[i]);"),
@@ -46,6 +46,24 @@ MUTANTS = {
     "composite adjoint remainder sign": ("dtau += dQ[ch] * (Tn * c[ch] - rest);",
                                          "dtau += dQ[ch] * (Tn * c[ch] + rest);"),
     "composite adjoint activation": ("const double ds = sigmoid(q[0]) * dl;", "const double ds = dl;"),
+    # the magnitude outputs every GPU tolerance is scaled by
+    "fwd magnitude drops the weight": ("acc += fabs(w64[k] * table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j));",
+                                       "acc += fabs(table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j));"),
+    "adjoint magnitude drops the weight": ("if (absmag) absmag[slot] += fabs(w64[k] * g);",
+                                           "if (absmag) absmag[slot] += fabs(g);"),
+    "input grad magnitude skew chain": ("ax[m] += (double)sigma[l] * (a[m] + Fn * as);",
+                                        "ax[m] += (double)sigma[l] * a[m];"),
+    "input grad magnitude sum of rows": ("a[axis] += fabs((t[k + 1][j] - t[k][j]) * d[j]);",
+                                         "a[axis] += (fabs(t[k + 1][j]) + fabs(t[k][j])) * fabs(d[j]);"),
+    "input grad grid magnitude factor": ("a[i] += fabs(c * t[b][j] * d[j]);", "a[i] += fabs(t[b][j] * d[j]);"),
+    "mlp fwd magnitude unmasked": ("a1[o] = s > 0.0 ? sa : 0.0;", "a1[o] = sa;"),
+    "mlp bwd magnitude unmasked": ("mh1[i] = h1[i] > 0.0 ? m : 0.0;", "mh1[i] = m;"),
+    "mlp bwd magnitude dW3 factor": ("if (with_mag) mag_dW3[o * H + i] += fabs(dy[o]) * fabs(OP(h2[i]));",
+                                     "if (with_mag) mag_dW3[o * H + i] += fabs(dy[o]);"),
+    "mlp bwd exact mode rounds": ("#define OP(v) (mode == ORC_MLP_BF16 ? orc_round_bf16(v) : (v))",
+                                  "#define OP(v) (orc_round_bf16(v))"),
+    "composite magnitude remainder": ("atau += fabs(dQ[ch]) * (Tn * fabs(c[ch]) + fabs(Q[ch]) + fabs(part[ch]));",
+                                      "atau += fabs(dQ[ch]) * (Tn * fabs(c[ch]) + fabs(Q[ch]));"),
 }
 
 

@@ -691,3 +691,184 @@ def test_input_grad_central_differences(n, cell):
         np.testing.assert_allclose(ana[smooth, m], ((fu - fd) / (2 * h))[smooth], rtol=0, atol=2e-3 * scale)
         checked += smooth.sum()
     assert checked > 0
+
+
+# ---------------------------------------------------------------- magnitudes
+# Every GPU tolerance is a multiple of one of the oracle's magnitude outputs
+# (sums of the absolute values of the terms).  Each is pinned where its
+# terms cannot cancel -- non-negative operands, or tables whose row
+# differences all have one sign -- so the magnitude must equal the signed
+# result exactly; and everywhere it must bound the signed result.
+
+def test_encode_fwd_absmag_pins():
+    rng = np.random.default_rng(60)
+    for n, cell in [(2, oracle.SIMPLEX), (3, oracle.SIMPLEX), (2, oracle.GRID), (4, oracle.GRID)]:
+        res = [5, 9, 17]
+        e = oracle.Encoding(n, res, 12, n_feat=2, cell=cell)
+        x = inputs.uniform_points(2000, n, 61 + n)
+        tab = rng.uniform(0, 1, (3, 1 << 12, 2)).astype(np.float32)
+        np.testing.assert_array_equal(oracle.encode_fwd_absmag(e, x, tab), oracle.encode_fwd(e, x, tab))
+        signed = rng.uniform(-1, 1, tab.shape).astype(np.float32)
+        mag = oracle.encode_fwd_absmag(e, x, signed)
+        np.testing.assert_array_equal(mag, oracle.encode_fwd(e, x, np.abs(signed)))
+        assert (mag >= np.abs(oracle.encode_fwd(e, x, signed))).all()
+
+
+def test_encode_bwd_absmag_pins():
+    rng = np.random.default_rng(62)
+    for n, cell in [(2, oracle.SIMPLEX), (3, oracle.GRID)]:
+        e = oracle.Encoding(n, [4, 7], 10, n_feat=2, cell=cell)
+        x = inputs.uniform_points(3000, n, 63)
+        d = rng.uniform(0, 1, (3000, 4))
+        g, mag, _ = oracle.encode_bwd(e, x, d, with_stats=True)
+        np.testing.assert_array_equal(mag, g)
+        g2, mag2, _ = oracle.encode_bwd(e, x, d - 0.5, with_stats=True)
+        assert (mag2 >= np.abs(g2)).all()
+        np.testing.assert_array_equal(mag2, oracle.encode_bwd(e, x, np.abs(d - 0.5)))
+
+
+def test_input_grad_magnitude_pins():
+    # simplex: tables increasing by one per lattice step, so every walk step's
+    # row difference is positive; positive output gradients
+    n, res, log2_T = 2, [16, 24, 36, 54], 14
+    boxes = _injective_box(n, res, log2_T)
+    tab = np.zeros((len(res), 1 << log2_T, 2), np.float32)
+    for l, (verts, slots) in enumerate(boxes):
+        tab[l, slots, 0] = verts.sum(axis=1) + 1.0
+        tab[l, slots, 1] = 3.0 * (verts.sum(axis=1) + 1.0)
+    e = oracle.Encoding(n, res, log2_T, n_feat=2)
+    x = inputs.uniform_points(1500, n, 64)
+    d = np.random.default_rng(65).uniform(0, 1, (1500, 8))
+    g, mag = oracle.encode_input_grad(e, x, tab, d, with_mag=True)
+    np.testing.assert_array_equal(mag, g)
+    # grid, one level: rows alternating in sign with the parity of v_0, so the
+    # terms of the derivative along axis 0 share one sign in every cell
+    boxes = _injective_box(2, [16], 14)
+    tab = np.zeros((1, 1 << 14, 1), np.float32)
+    verts, slots = boxes[0]
+    tab[0, slots, 0] = np.where(verts[:, 0] % 2 == 1, 1.0, -1.0) * (1.0 + verts[:, 0] + 2.0 * verts[:, 1])
+    e = oracle.Encoding(2, [16], 14, n_feat=1, cell=oracle.GRID)
+    d = np.random.default_rng(66).uniform(0, 1, (1500, 1))
+    g, mag = oracle.encode_input_grad(e, x, tab, d, with_mag=True)
+    np.testing.assert_array_equal(mag[:, 0], np.abs(g[:, 0]))
+    # generic tables: a bound
+    tab = np.random.default_rng(67).uniform(-1, 1, (4, 1 << 14, 2)).astype(np.float32)
+    for cell in (oracle.SIMPLEX, oracle.GRID):
+        e = oracle.Encoding(2, res, 14, n_feat=2, cell=cell)
+        g, mag = oracle.encode_input_grad(e, x, tab, np.random.default_rng(68).uniform(-1, 1, (1500, 8)),
+                                          with_mag=True)
+        assert (mag >= np.abs(g)).all()
+
+
+def _mlp_pin_operands(rng, d_in=32, H=64, d_out=16, N=400, dead=8):
+    """Small non-negative integers (every binary16 rounding and every sum
+    exact), with `dead` layer-1 units whose weights are all negative: those
+    units are inactive for every non-negative input."""
+    W1 = rng.integers(0, 3, (H, d_in)).astype(np.float64)
+    W1[:dead] = -rng.integers(1, 3, (dead, d_in))
+    W2 = (rng.integers(0, 2, (H, H)) * (rng.random((H, H)) < 0.2)).astype(np.float64)
+    W3 = (rng.integers(0, 2, (d_out, H)) * (rng.random((d_out, H)) < 0.3)).astype(np.float64)
+    x = rng.integers(0, 2, (N, d_in)).astype(np.float64)
+    return x.astype(np.float16), W1.astype(np.float16), W2.astype(np.float16), W3.astype(np.float16)
+
+
+def test_mlp_fwd_magnitude_pins():
+    rng = np.random.default_rng(70)
+    x, W1, W2, W3 = _mlp_pin_operands(rng)
+    y, mag = oracle.mlp_fwd(x, W1, W2, W3, with_absmag=True)
+    assert y.max() > 0
+    np.testing.assert_array_equal(mag, y)
+    # generic operands: the magnitude bounds the output and grows with |W3|
+    W1, W2, W3 = inputs.mlp_weights(32, 64, 3, 71)
+    x = inputs.features_f16(500, 32, 72)
+    y, mag = oracle.mlp_fwd(x, W1, W2, W3, with_absmag=True)
+    assert (mag >= np.abs(y)).all()
+    _, mag2 = oracle.mlp_fwd(x, W1, W2, (2 * W3.astype(np.float32)).astype(np.float16), with_absmag=True)
+    np.testing.assert_allclose(mag2, 2 * mag, rtol=1e-15)
+
+
+def test_mlp_bwd_magnitude_pins():
+    rng = np.random.default_rng(73)
+    x, W1, W2, W3 = _mlp_pin_operands(rng)
+    dy = rng.integers(0, 3, (len(x), 16)).astype(np.float32)
+    o = oracle.mlp_bwd(x, W1, W2, W3, dy, mode=oracle.MLP_EXACT, with_mag=True)
+    assert o["dW1"].max() > 0 and o["d_x"].max() > 0
+    for k in ("d_x", "dW1", "dW2", "dW3"):
+        np.testing.assert_array_equal(o["mag_" + k], o[k])
+    # generic operands (both modes): a bound
+    W1, W2, W3 = inputs.mlp_weights(32, 64, 4, 74)
+    x = inputs.features_f16(300, 32, 75)
+    dy = inputs.gradients(300, 4, 76)
+    for mode in (oracle.MLP_BF16, oracle.MLP_EXACT):
+        o = oracle.mlp_bwd(x, W1, W2, W3, dy, mode=mode, with_mag=True)
+        for k in ("d_x", "dW1", "dW2", "dW3"):
+            assert (o["mag_" + k] >= np.abs(o[k]) * (1 - 1e-12)).all(), (mode, k)
+
+
+def test_composite_adjoint_magnitude_single_sample():
+    """One sample per ray: nothing lies behind the sample, so the magnitude
+    of the density term is sigmoid(raw_0) delta sum_ch |dQ| (e^-tau c +
+    2 w c) (the transmittance past the sample, the total and the partial
+    sum, each w c), and of each colour term |dQ| w c (1 - c)."""
+    rng = np.random.default_rng(77)
+    R = 50
+    raw = rng.normal(size=(R, 1, 4)).astype(np.float32)
+    delta = rng.uniform(0.01, 0.5, (R, 1)).astype(np.float32)
+    dQ = rng.normal(size=(R, 4))
+    _, mag = oracle.composite_bwd(raw, delta, dQ, with_mag=True)
+    tau = _softplus(raw[:, 0, 0]) * delta[:, 0]
+    w = -np.expm1(-tau)
+    c = np.concatenate([_sigmoid(raw[:, 0, 1:]), np.ones((R, 1))], axis=1)
+    m0 = _sigmoid(raw[:, 0, 0]) * delta[:, 0] * np.sum(np.abs(dQ) * (np.exp(-tau)[:, None] * c + 2 * w[:, None] * c),
+                                                        axis=1)
+    np.testing.assert_allclose(mag[:, 0, 0], m0, rtol=1e-12)
+    np.testing.assert_allclose(mag[:, 0, 1:], np.abs(dQ[:, :3]) * (w[:, None] * c[:, :3] * (1 - c[:, :3])),
+                               rtol=1e-12)
+    # many samples: a bound
+    raw = rng.normal(size=(20, 64, 4)).astype(np.float32)
+    delta = rng.uniform(0.001, 0.05, (20, 64)).astype(np.float32)
+    d, mag = oracle.composite_bwd(raw, delta, rng.normal(size=(20, 4)), with_mag=True)
+    assert (mag >= np.abs(d)).all()
+
+
+def test_mlp_bwd_exact_mode_matches_autograd():
+    """The exact mode is the network's derivative: float64 autograd of the
+    same network, activations rounded to binary16 in the forward (straight
+    through in the backward), on generic inputs."""
+    torch = pytest.importorskip("torch")
+    for d_out in (3, 16):
+        W1, W2, W3 = inputs.mlp_weights(32, 64, d_out, 78 + d_out)
+        x = inputs.features_f16(400, 32, 80 + d_out)
+        dy = inputs.gradients(400, d_out, 82 + d_out)
+        o = oracle.mlp_bwd(x, W1, W2, W3, dy, mode=oracle.MLP_EXACT)
+        tx = torch.tensor(x.astype(np.float64), requires_grad=True)
+        tW = [torch.tensor(w.astype(np.float64), requires_grad=True) for w in (W1, W2, W3)]
+
+        def r16(h):
+            # numpy rounds binary64 to binary16 directly (torch goes through
+            # binary32 and can round twice)
+            q = torch.from_numpy(h.detach().numpy().astype(np.float16).astype(np.float64))
+            return h + (q - h).detach()
+
+        y = r16(torch.relu(r16(torch.relu(tx @ tW[0].T)) @ tW[1].T)) @ tW[2].T
+        y.backward(torch.tensor(dy.astype(np.float64)))
+        for k, ref in [("d_x", tx.grad), ("dW1", tW[0].grad), ("dW2", tW[1].grad), ("dW3", tW[2].grad)]:
+            r = ref.numpy()
+            np.testing.assert_allclose(o[k], r, rtol=1e-11, atol=1e-13 * np.abs(r).max(), err_msg=k)
+
+
+def test_mlp_bwd_bf16_mode_within_operand_rounding():
+    """The bfloat16 mode differs from the exact mode by the rounding of the
+    operands (each at most 2^-8 relative): at most 2^-8 times the number
+    of rounded operands on the path, times the magnitude."""
+    W1, W2, W3 = inputs.mlp_weights(32, 64, 3, 90)
+    x = inputs.features_f16(600, 32, 91)
+    dy = inputs.gradients(600, 3, 92)
+    a = oracle.mlp_bwd(x, W1, W2, W3, dy, mode=oracle.MLP_BF16)
+    b = oracle.mlp_bwd(x, W1, W2, W3, dy, mode=oracle.MLP_EXACT, with_mag=True)
+    # rounded operands on each result's path: dW3 dy, h2; dW2 dy, W3, dh2, h1;
+    # dW1 dy, W3, dh2, W2, dh1, x; d_x dy, W3, dh2, W2, dh1, W1
+    for k, r in [("dW3", 2), ("dW2", 4), ("dW1", 6), ("d_x", 6)]:
+        bound = r * 2.0 ** -8 * 1.01 * b["mag_" + k]
+        assert (np.abs(a[k] - b[k]) <= bound + 1e-300).all(), k
+        assert np.abs(a[k] - b[k]).max() > 0  # the modes do differ
