@@ -8,9 +8,12 @@ A step is the whole hot path on one batch already resident in GPU memory:
   encode forward -> MLP forward -> L2 loss gradient -> MLP backward ->
   encode adjoint -> Adam on the tables (binary32 master + binary16 copy,
   gradient cleared) -> Adam on the MLP weights.
-Prints one JSON line.  The same step with the 2^n-corner grid baseline, the
-encoding kernels alone (simplex and grid), and the CPU oracle on a bounded
-sample are reported beside it.
+The same step with the 2^n-corner grid baseline, the encoding kernels alone
+(simplex and grid, with their fraction of the measured random-gather
+ceiling), the volume workload, serving, and the CPU oracle on a bounded
+sample are reported beside it.  The full record goes to a JSON file
+(--detail-out); stdout ends with a few '#' summary lines and one compact
+JSON line (under 4 KB) carrying the headline figures.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -29,6 +32,63 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+LINE_BYTES = 128  # cache line of gfx950's vector L1 and L2
+# one 64-byte HBM access per random gather: the theoretical random-gather rate
+HBM_RANDOM_GATHERS_PER_S = HBM_PEAK_GBS * 1e9 / 64.0
+DETAIL_DEFAULT = os.path.join("gpurun_out", "bench_detail.json")
+
+
+def expected_unique(M, k):
+    """Expected number of distinct items among k uniform draws from M."""
+    M = float(M)
+    return -M * np.expm1(k * np.log1p(-1.0 / M)) if M > 1 else 1.0
+
+
+def wave_unique_lines(idx, log2_T, row_bytes, wave=64):
+    """Mean number of distinct cache lines one wave (`wave` consecutive
+    points) touches at each level, over all its vertices: idx [N, L, V]
+    slots in launch order.  Lines shared by lanes or by the vertices of one
+    lane count once (an optimistic count for the kernel)."""
+    N, L, V = idx.shape
+    W = N // wave
+    a = idx[:W * wave].astype(np.int64).reshape(W, wave, L, V).transpose(0, 2, 1, 3).reshape(W, L, wave * V)
+    lines = np.sort((a * row_bytes) // LINE_BYTES, axis=2)
+    uniq = 1 + np.count_nonzero(np.diff(lines, axis=2), axis=2)
+    return uniq.mean(axis=0)
+
+
+def level_footprints(sigma, reach, n, log2_T, row_bytes, simplex):
+    """Bytes of whole cache lines each level can touch: the lattice box the
+    unit cube reaches (extent floor(sigma * reach) + 2 per axis), its
+    vertices hashed uniformly over the level's T rows."""
+    T = 1 << log2_T
+    M_tot = max(1.0, T * row_bytes / LINE_BYTES)
+    out = []
+    for s in sigma:
+        box = (np.floor(float(s) * reach) + 2.0) ** n
+        out.append(LINE_BYTES * expected_unique(M_tot, min(box, float(T))))
+    return out
+
+
+def line_rate(probe, nbytes):
+    """Measured random-gather rate at a buffer of nbytes, in distinct line
+    requests per second: the probe's gathers/s (log-linear interpolation
+    between its power-of-two sizes, clamped to its range) times the
+    fraction of a wave's 64 gathers that fall on distinct lines."""
+    sizes = np.array(sorted(probe), dtype=np.float64)
+    rates = np.array([probe[int(k)] for k in sizes])
+    x = np.clip(np.log2(max(nbytes, 1.0)), np.log2(sizes[0]), np.log2(sizes[-1]))
+    g = float(np.interp(x, np.log2(sizes), rates))
+    M = 2.0 ** x / LINE_BYTES
+    return g * expected_unique(M, 64) / 64.0
+
+
+def gather_ceiling_ms(N, unique_per_wave, footprints, probe, wave=64):
+    """Time the memory system needs for one pass of the encoding's gathers
+    at the measured random-gather rates: per level, the waves' distinct
+    line requests at that level's footprint."""
+    waves = N / wave
+    return 1e3 * sum(waves * u / line_rate(probe, f) for u, f in zip(unique_per_wave, footprints))
 
 
 COPY_ELEMS = 1 << 26  # calibration copy: 256 MiB read, 128 MiB written
@@ -48,37 +108,46 @@ def _sources_digest():
     return h.hexdigest()
 
 
+# Read bytes per dispatch from the L2's read requests to memory, by request
+# size.  (rocprofv3's derived FETCH_SIZE takes the 128-byte requests from
+# TCC_BUBBLE, which reads 0 on gfx950, and so counts each 128-byte line fill
+# as 64 bytes: half of a streaming kernel's reads.)
+READ_COUNTERS = {"TCC_EA0_RDREQ_128B_sum": 128.0, "TCC_EA0_RDREQ_64B_sum": 64.0, "TCC_EA0_RDREQ_32B_sum": 32.0}
+
+
 def _counter_rows(path):
-    """(kernel name, counter value in KiB) per dispatch of a rocprofv3 --pmc CSV."""
+    """{(dispatch id, kernel name): {counter: value}} of a rocprofv3 --pmc CSV."""
     import csv
-    out = []
+    out = {}
     with open(path, newline="") as fh:
         for r in csv.DictReader(fh):
-            out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+            out.setdefault((int(r["Dispatch_Id"]), r["Kernel_Name"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
     return out
 
 
-def write_traffic(fetch_csv, write_csv, workload):
-    """HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
-    counter runs of `--pmc-pass` on `workload`, each scaled by what the counter
-    reads for the calibration copy of known size (the last cast kernel
-    dispatch)."""
+def write_traffic(read_csv, write_csv, workload):
+    """HBM bytes per launch of the dominant kernel from two counter runs of
+    `--pmc-pass` on `workload`: bytes read from the read requests by size
+    (READ_COUNTERS), bytes written from WRITE_SIZE (KiB).  The calibration
+    copy of known size (the last cast kernel dispatch) is reported beside
+    them as a check of both."""
     res = {"sources_sha256": _sources_digest(), "workload": workload, "copy_elems": COPY_ELEMS, "kernels": {}}
-    known = {"FETCH_SIZE": COPY_ELEMS * 4 / 1024.0, "WRITE_SIZE": COPY_ELEMS * 2 / 1024.0}
-    rows = {"FETCH_SIZE": _counter_rows(fetch_csv), "WRITE_SIZE": _counter_rows(write_csv)}
-    factor = {}
-    for c, rr in rows.items():
-        copy = [v for k, v in rr if "cast_kernel" in k]
-        factor[c] = copy[-1] / known[c]
-    res["factor"] = factor
+    reads = sorted(_counter_rows(read_csv).items())
+    writes = sorted(_counter_rows(write_csv).items())
+
+    def read_bytes(c):
+        return sum(c.get(k, 0.0) * b for k, b in READ_COUNTERS.items())
+
+    copy_r = [read_bytes(c) for (_, k), c in reads if "cast_kernel" in k][-1]
+    copy_w = [c["WRITE_SIZE"] * 1024.0 for (_, k), c in writes if "cast_kernel" in k][-1]
+    res["copy_check"] = {"read_bytes": copy_r, "read_expected": COPY_ELEMS * 4.0,
+                         "written_bytes": copy_w, "written_expected": COPY_ELEMS * 2.0}
     for name, (sym, tmpl) in TRAFFIC_KERNELS.items():
-        entry = {}
-        for c, rr in rows.items():
-            vals = [v for k, v in rr if sym in k and tmpl in k.split(sym, 1)[1]]
-            entry[c + "_KiB_raw"] = vals[-1]
-            entry[c + "_bytes"] = vals[-1] * 1024.0 / factor[c]
-        entry["bytes"] = entry["FETCH_SIZE_bytes"] + entry["WRITE_SIZE_bytes"]
-        res["kernels"][name] = entry
+        def mine(k):
+            return sym in k and tmpl in k.split(sym, 1)[1]
+        r = [read_bytes(c) for (_, k), c in reads if mine(k)][-1]
+        w = [c["WRITE_SIZE"] * 1024.0 for (_, k), c in writes if mine(k)][-1]
+        res["kernels"][name] = {"read_bytes": r, "written_bytes": w, "bytes": r + w}
     with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res))
@@ -399,17 +468,68 @@ def time_encode_only(ts, reps=20):
             "fwd_bwd_points_per_s": ts.N / ((f + b) * 1e-3)}
 
 
+def probe_gather_rates(log2_min=12, log2_max=28, threads=1 << 20, per_thread=64, reps=5):
+    """Uniformly random 4-byte gathers (spx_gather_probe) from buffers of
+    2^log2_min .. 2^log2_max bytes: {bytes: gathers/s}, the best of `reps`
+    timed launches after two untimed ones."""
+    import torch
+    from paper_2311_15439_amd import spx
+    buf = torch.zeros(1 << (log2_max - 2), dtype=torch.int32, device="cuda")
+    out = torch.empty(threads, dtype=torch.int32, device="cuda")
+    rates = {}
+    for e in range(log2_min, log2_max + 1):
+        view = buf[: 1 << (e - 2)]
+        for _ in range(2):
+            spx.spx_gather_probe(view, threads, per_thread, e, out)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        for r in range(reps):
+            ev[2 * r].record()
+            spx.spx_gather_probe(view, threads, per_thread, 1000 * r + e, out)
+            ev[2 * r + 1].record()
+        torch.cuda.synchronize()
+        ms = min(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(reps))
+        rates[1 << e] = threads * per_thread / (ms * 1e-3)
+    del buf, out
+    return rates
+
+
+def encode_gather_ceiling(enc, pts, res_sigma, probe, sample=1 << 16):
+    """The forward's gather ceiling on these points: distinct lines per
+    wave and level from the lookup's slots on the first `sample` points (in
+    launch order), each level's footprint, and the time the measured
+    random-gather rates need for all N points."""
+    import torch
+    from paper_2311_15439_amd import spx
+    N = pts.shape[0]
+    S = min(sample, N) // 64 * 64
+    V = enc.n_vertices
+    idx = torch.empty((S, enc.n_levels, V), dtype=torch.int32, device="cuda")
+    spx.spx_encode_debug(enc, pts[:S].contiguous(), idx=idx)
+    slots = idx.cpu().numpy().view(np.uint32)
+    row = enc.n_feat * (2 if enc.table_dtype == spx.SPX_F16 else 4)
+    uniq = wave_unique_lines(slots, enc.log2_T, row)
+    simplex = enc.cell == spx.SPX_SIMPLEX
+    reach = float(np.sqrt(enc.n_dims + 1.0)) if simplex else 1.0
+    foot = level_footprints(res_sigma, reach, enc.n_dims, enc.log2_T, row, simplex)
+    return {"ceiling_ms": gather_ceiling_ms(N, uniq, foot, probe),
+            "lines_per_point": float(np.sum(uniq) / 64.0),
+            "footprint_MiB": [round(f / 2 ** 20, 3) for f in foot]}
+
+
 def _quantiles(ms):
     q = np.percentile(np.asarray(ms), [10, 50, 90])
     return {"p10_ms": float(q[0]), "median_ms": float(q[1]), "p90_ms": float(q[2])}
 
 
-def time_encode_sweep(reps=30, warm=5):
+def time_encode_sweep(reps=30, warm=5, probe=None):
     """Encoding alone, simplex vs the 2^n grid on identical points and tables:
-    the volume workload (n=3, L=16, T=2^19, 2^21 ray samples) and the
-    dimension sweep (n=2..6, L=8, T=2^20, 2^20 uniform points).  Forward, and
-    forward + binned adjoint (with the gradient clearing, timed on its own
-    too); median and p10/p90 over per-repetition events."""
+    the image workload, the volume workload (n=3, L=16, T=2^19, 2^21 ray
+    samples) and the dimension sweep (n=2..6, L=8, T=2^20, 2^20 uniform
+    points).  Forward, and forward + binned adjoint (with the gradient
+    clearing, timed on its own too); median and p10/p90 over per-repetition
+    events.  Gather fractions are the measured random-gather ceiling's time
+    (encode_gather_ceiling) over the kernel's time; forward + adjoint touch
+    every row twice."""
     import torch
     from paper_2311_15439_amd import inputs, spx
     dev = "cuda"
@@ -477,6 +597,7 @@ def time_encode_sweep(reps=30, warm=5):
                 k["bytes"] += nbytes
             for k in bwd_kernels.values():
                 k["GB_s"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else None
+            ceil = encode_gather_ceiling(enc, pts, spx.spx_level_scales(enc), probe) if probe else None
             tw = [e[0].elapsed_time(e[1]) for e in ev]
             f = [e[1].elapsed_time(e[2]) for e in ev]
             z = [e[2].elapsed_time(e[3]) for e in ev]
@@ -489,11 +610,12 @@ def time_encode_sweep(reps=30, warm=5):
                           "gather_twin": wq, "bwd_kernels": bwd_kernels, "input_grad_ms": input_grad_ms,
                           "fwd_points_per_s": N / (fq["median_ms"] * 1e-3),
                           "fwd_bwd_points_per_s": N / (tq["median_ms"] * 1e-3),
-                          "twin_gathers_per_s": gathers / (wq["median_ms"] * 1e-3),
-                          # fraction of the gather roofline: the twin's rate is the ceiling for one
-                          # gather per vertex and level; forward + adjoint touch every row twice
-                          "fwd_gather_frac": wq["median_ms"] / fq["median_ms"],
-                          "fwd_bwd_gather_frac": 2.0 * wq["median_ms"] / tq["median_ms"]}
+                          "fwd_gathers_per_s": gathers / (fq["median_ms"] * 1e-3),
+                          "twin_gathers_per_s": gathers / (wq["median_ms"] * 1e-3)}
+            if ceil:
+                row[cname]["gather_ceiling"] = ceil
+                row[cname]["fwd_gather_frac"] = ceil["ceiling_ms"] / fq["median_ms"]
+                row[cname]["fwd_bwd_gather_frac"] = 2.0 * ceil["ceiling_ms"] / tq["median_ms"]
             del ws
         row["simplex_speedup_fwd"] = row["grid"]["fwd"]["median_ms"] / row["simplex"]["fwd"]["median_ms"]
         row["simplex_speedup_fwd_bwd"] = row["grid"]["fwd_bwd"]["median_ms"] / row["simplex"]["fwd_bwd"]["median_ms"]
@@ -625,39 +747,85 @@ def time_fused_query(ts, reps=20):
     return {"fused_ms": e[0].elapsed_time(e[1]) / reps, "separate_ms": e[1].elapsed_time(e[2]) / reps}
 
 
-def cpu_encode_rates(S=1 << 15):
-    """The oracle's encoding forward on the host cores (all threads, then
-    one): the plain 2-D configuration in full and the dimension sweep on a
-    sample of S points, simplex and grid (points/s; beside the GPU table
-    above, as the paper reports CPU timings per dimension)."""
+def cpu_encode_rates(S=1 << 16):
+    """The oracle's encoding on the host cores, simplex and grid (points/s;
+    beside the GPU tables, as the paper reports CPU timings per dimension):
+    the plain 2-D configuration's forward in full (all threads, then one),
+    and forward plus adjoint on S points of the volume workload and of the
+    dimension sweep n=2..6 (the forward on all threads, the adjoint, a
+    binary64 sum in point order, on one)."""
     import oracle
     from paper_2311_15439_amd import inputs
     threads = oracle.max_threads()
     out = {"threads_all": threads, "sample_points": S}
-    cases = [inputs.PLAIN_2D] + [inputs.sweep_workload(n) for n in range(2, 7)]
-    data = []
-    for w in cases:
-        N = w.n_points if w is inputs.PLAIN_2D else S
-        pts = inputs.uniform_points(N, w.n_dims, w.seed_points)
-        tab = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, w.table_f16)
-        res = oracle.level_resolutions(w.n_min, w.growth, w.n_levels)
-        data.append((w, N, pts, tab, res))
+    p = inputs.PLAIN_2D
+    pts = inputs.uniform_points(p.n_points, p.n_dims, p.seed_points)
+    tab = inputs.tables(p.n_levels, 1 << p.log2_T, p.n_feat, p.table_init, p.seed_tables, p.table_f16)
+    res = oracle.level_resolutions(p.n_min, p.growth, p.n_levels)
     try:
         for nt in (threads, 1):
             oracle.set_threads(nt)
-            w, N, pts, tab, res = data[0]
-            oracle.encode_fwd(oracle.Encoding(w.n_dims, list(res), w.log2_T, w.n_feat), pts[:1024], tab)  # warm-up
-            for w, N, pts, tab, res in data:
-                row = out.setdefault(w.name, {})
-                for cell, cname in ((oracle.SIMPLEX, "simplex"), (oracle.GRID, "grid")):
-                    e = oracle.Encoding(w.n_dims, list(res), w.log2_T, w.n_feat,
-                                        table_dtype=oracle.F16 if w.table_f16 else oracle.F32, cell=cell)
-                    t0 = time.perf_counter()
-                    oracle.encode_fwd(e, pts, tab)
-                    row[f"{cname}_points_per_s_{nt}t"] = N / (time.perf_counter() - t0)
+            oracle.encode_fwd(oracle.Encoding(p.n_dims, list(res), p.log2_T, p.n_feat), pts[:1024], tab)  # warm-up
+            for cell, cname in ((oracle.SIMPLEX, "simplex"), (oracle.GRID, "grid")):
+                e = oracle.Encoding(p.n_dims, list(res), p.log2_T, p.n_feat, table_dtype=oracle.F32, cell=cell)
+                t0 = time.perf_counter()
+                oracle.encode_fwd(e, pts, tab)
+                out.setdefault(p.name, {})[f"{cname}_fwd_points_per_s_{nt}t"] = p.n_points / (time.perf_counter() - t0)
     finally:
         oracle.set_threads(threads)
+    for w in [inputs.VOLUME_3D] + [inputs.sweep_workload(n) for n in range(2, 7)]:
+        if w.name.startswith("volume"):
+            pts = inputs.ray_points(S // 256, 256, w.seed_points)
+        else:
+            pts = inputs.uniform_points(S, w.n_dims, w.seed_points)
+        tab = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, True)
+        res = oracle.level_resolutions(w.n_min, w.growth, w.n_levels)
+        dout = inputs.gradients(S, w.n_levels * w.n_feat, w.seed_points + 50).astype(np.float64)
+        row = out.setdefault(w.name, {})
+        for cell, cname in ((oracle.SIMPLEX, "simplex"), (oracle.GRID, "grid")):
+            e = oracle.Encoding(w.n_dims, list(res), w.log2_T, w.n_feat, table_dtype=oracle.F16, cell=cell)
+            t0 = time.perf_counter()
+            oracle.encode_fwd(e, pts, tab)
+            t1 = time.perf_counter()
+            oracle.encode_bwd(e, pts, dout)
+            t2 = time.perf_counter()
+            row[f"{cname}_fwd_points_per_s"] = S / (t1 - t0)
+            row[f"{cname}_fwd_bwd_points_per_s"] = S / (t2 - t0)
     return out
+
+
+def cpu_identity():
+    """The host's CPU model (first /proc/cpuinfo entry) and usable cores."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return model, cores
+
+
+def use_timing_oracle():
+    """Build the oracle for this host (-O3 -march=native) in a temporary
+    directory and load it; the parity build is used if that fails.
+    Returns the build's description."""
+    import tempfile
+
+    import oracle
+    try:
+        path = oracle.build_timing(os.path.join(tempfile.mkdtemp(prefix="spx_oracle_"), "liboracle_native.so"))
+        oracle.use_library(path)
+        return "gcc -O3 -march=native -ffp-contract=off -fopenmp"
+    except Exception as e:  # noqa: BLE001  (the parity build still times the oracle)
+        print(f"# timing build of the oracle failed ({e}); timing the parity build", file=sys.stderr, flush=True)
+        return "gcc -O2 -ffp-contract=off -fopenmp (parity build)"
 
 
 def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
@@ -685,11 +853,13 @@ def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
     oracle.adam_step(flat, flat * 0.01, np.zeros(P, np.float32), np.zeros(P, np.float32), 1e-2, 0.9, 0.99, 1e-15, 1)
     t_adam = (time.perf_counter() - t0) * 16
     t_step = t_pts * (w.n_points / S) + t_adam
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.max_threads()
+    model, ncpu = cpu_identity()
     return {"value": w.n_points / t_step, "unit": "points/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle training step on {S} of the {w.n_points} points ({t_pts:.2f} s) plus Adam on 1/16 "
                       f"of the tables ({t_adam / 16:.2f} s), scaled to one {w.n_points}-point step; "
-                      f"encode fwd and MLP fwd use {threads} OpenMP threads, the rest one thread"}
+                      f"encode fwd and MLP fwd on {threads} OpenMP threads, the rest on one",
+            "cpu_model": model, "host_cores": ncpu}
 
 
 def serving_bench(n_fields=8, n_requests=2000, warm=200, loads=(0.5, 0.8), train_steps=30):
@@ -799,10 +969,12 @@ def main():
                     help="skip the volume workload's training step (simplex vs grid) and its accuracy comparison")
     ap.add_argument("--no-render", action="store_true",
                     help="skip the volume-rendering training step (compositing along rays), simplex vs grid")
+    ap.add_argument("--detail-out", default=DETAIL_DEFAULT,
+                    help="file for the full JSON record (the last stdout line is a compact summary)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run two training steps and a binary32->binary16 copy of 2^26 elements, then exit "
                          "(the program profiled by the rocprofv3 --pmc traffic runs)")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--write-traffic", nargs=2, metavar=("READ_CSV", "WRITE_CSV"),
                     help="turn the counter CSVs of the two --pmc runs (of --pmc-pass on --workload) into "
                          + TRAFFIC_FILE + " and exit")
     args = ap.parse_args()
@@ -884,9 +1056,11 @@ def main():
     if not args.no_render and w.name.startswith("image"):
         render = render_bench()
 
-    sweep = None
+    sweep, probe = None, None
     if not args.no_sweep:
-        sweep = time_encode_sweep()
+        print("# random-gather probe", file=sys.stderr, flush=True)
+        probe = probe_gather_rates()
+        sweep = time_encode_sweep(probe=probe)
 
     serving = None
     if not args.no_serving:
@@ -900,28 +1074,18 @@ def main():
     cpu, cpu_rates = None, None
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
+        build = use_timing_oracle()
         cpu = cpu_baseline(w, host_tables, weights, batches[0])
+        cpu["build"] = build
         cpu_rates = cpu_encode_rates()
 
     value = w.n_points / (ms * 1e-3)
-    line = {
-        "metric": "encoded points/s fwd & fwd+bwd, simplex vs 2^n-grid same GPU; serving p50/p99 ms",
-        "value": value,
+    detail = {
         "value_is": ("points/s of the whole simplex training step (encode fwd, MLP fwd, loss gradient, MLP bwd, "
-                     "encode adjoint fused with Adam on the tables, Adam on the MLP) on the image workload; "
-                     "fwd-only, fwd+bwd and grid figures are under encode_sweep, grid_baseline_step, serving"),
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+                     "encode adjoint fused with Adam on the tables, Adam on the MLP) on the image workload"),
         "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f16 tables, f32 accumulate",
-        "data": "synthetic",
-        "config": {"workload": w.name + f", {w.n_points} points/step, MLP {w.n_levels * w.n_feat}-64-64-{d_out}",
-                   "levels": res, "parallelism": "single GPU"},
+        "config": {"workload": w.name, "points_per_step": w.n_points, "levels": res,
+                   "mlp": f"{w.n_levels * w.n_feat}-64-64-{d_out}"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, w.name),
                      "avg_ms": kern[dom]["timed_avg_ms"], "bytes_per_launch": kern[dom]["timed_bytes_per_launch"]},
@@ -934,6 +1098,7 @@ def main():
                                 "kernels_ms": grid["kernels_ms"]} if grid else None),
         "stream_reference": stream,
         "fused_query": fused_query,
+        "gather_probe_gathers_per_s": probe,
         "encode_sweep": sweep,
         "equal_accuracy": accuracy,
         "volume_step": volume,
@@ -941,7 +1106,114 @@ def main():
         "serving": serving,
         "wall_s_timed": wall,
     }
-    print(json.dumps(line), flush=True)
+    if args.detail_out:
+        d = os.path.dirname(args.detail_out)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.detail_out, "w") as fh:
+            json.dump(detail, fh, indent=1)
+    for ln in summary_lines(detail):
+        print(ln)
+    line = headline(detail, value, args.steps, args.warmup, args.detail_out)
+    print(json.dumps(line, separators=(",", ":")), flush=True)
+
+
+def _r(x, nd=4):
+    """Round to nd significant digits (None stays None)."""
+    if x is None:
+        return None
+    return float(f"{x:.{nd}g}")
+
+
+def summary_lines(d):
+    """Short human-readable lines (prefixed '#') printed before the JSON
+    line: one per section of the detail record."""
+    out = []
+    sw = d.get("encode_sweep") or {}
+    for name, row in sw.items():
+        s, g = row["simplex"], row["grid"]
+        out.append(f"# encode {name}: fwd {s['fwd']['median_ms']:.3f}/{g['fwd']['median_ms']:.3f} ms, "
+                   f"fwd+bwd {s['fwd_bwd']['median_ms']:.3f}/{g['fwd_bwd']['median_ms']:.3f} ms (simplex/grid); "
+                   f"gather frac simplex fwd {_r(s.get('fwd_gather_frac'), 3)} fwd+bwd "
+                   f"{_r(s.get('fwd_bwd_gather_frac'), 3)}")
+    acc = dict(d.get("equal_accuracy") or {})
+    if d.get("volume_step") and d["volume_step"].get("equal_accuracy"):
+        acc["volume"] = d["volume_step"]["equal_accuracy"]
+    for name, a in acc.items():
+        out.append(f"# accuracy {name}: PSNR simplex {a['simplex']['psnr_db']:.2f}, equal-memory "
+                   f"{a['simplex_equal_memory']['psnr_db']:.2f}, grid {a['grid']['psnr_db']:.2f} dB")
+    sv = d.get("serving")
+    if sv:
+        loads = ", ".join(f"{l['load']:.0%}: p50 {l['p50_ms']:.2f} p99 {l['p99_ms']:.2f} ms" for l in sv["loads"])
+        out.append(f"# serving: saturation {sv['saturation_points_per_s'] / 1e6:.0f} M points/s; {loads}")
+    return out
+
+
+def headline(d, value, steps, warmup, detail_path):
+    """The one JSON line the run ends with (compact; the full record is in
+    the detail file)."""
+    rf = d["roofline"]
+    cpu = d.get("cpu_baseline")
+    line = {
+        "metric": "encoded points/s fwd & fwd+bwd, simplex vs 2^n-grid same GPU; serving p50/p99 ms",
+        "value": _r(value, 6),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": _r(d["ms_per_step"], 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16 tables+features, f32 accumulate; MLP f16 MFMA fwd, bf16 MFMA operands bwd",
+        "data": "synthetic",
+        "config": {"workload": ("image-2d training step: n=2, L=16, T=2^22, F=2 f16 tables, N_l 16..32768, "
+                                "2^20 random pixels of a 16384^2 image per step, MLP 32-64-64-3, Adam"),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": rf["bound"], "kernel": rf["kernel"], "achieved": _r(rf["achieved"]),
+                     "peak": rf["peak"], "unit": rf["unit"], "frac": _r(rf["frac"]),
+                     "traffic": _r(rf["traffic"]), "avg_ms": _r(rf["avg_ms"]),
+                     "bytes_per_launch": _r(rf["bytes_per_launch"])},
+        "cpu_baseline": None if cpu is None else {
+            "value": _r(cpu["value"]), "unit": cpu["unit"], "cores": cpu["cores"], "kind": cpu["kind"],
+            "sample": "oracle step on 2^16 of 2^20 points + Adam on 1/16 of the tables, scaled",
+            "cpu_model": cpu.get("cpu_model"), "build": cpu.get("build")},
+    }
+    g = d.get("grid_baseline_step")
+    if g:
+        line["grid_step"] = {"points_per_s": _r(g["points_per_s"]), "ms_per_step": _r(g["ms_per_step"]),
+                             "simplex_speedup": _r(g["ms_per_step"] / d["ms_per_step"], 3)}
+    sw = d.get("encode_sweep")
+    if sw:
+        enc = {"cols": ["fwd_pts_s", "fwd_bwd_pts_s", "grid_fwd_pts_s", "grid_fwd_bwd_pts_s",
+                        "gather_frac_fwd", "gather_frac_fwd_bwd"]}
+        for name, row in sw.items():
+            s, gr = row["simplex"], row["grid"]
+            enc[name.split(" L=")[0]] = [_r(s["fwd_points_per_s"], 3), _r(s["fwd_bwd_points_per_s"], 3),
+                                        _r(gr["fwd_points_per_s"], 3), _r(gr["fwd_bwd_points_per_s"], 3),
+                                        _r(s.get("fwd_gather_frac"), 3), _r(s.get("fwd_bwd_gather_frac"), 3)]
+        line["encode"] = enc
+    acc = {}
+    for name, a in (d.get("equal_accuracy") or {}).items():
+        acc[name.split(" ")[0]] = [_r(a["simplex_minus_grid_db"], 3), _r(a["simplex_equal_memory_minus_grid_db"], 3)]
+    vol = d.get("volume_step")
+    if vol:
+        line["volume_step"] = {"points_per_s": _r(vol["simplex"]["points_per_s"]),
+                               "simplex_speedup": _r(vol["simplex_speedup"], 3)}
+        if vol.get("equal_accuracy"):
+            a = vol["equal_accuracy"]
+            acc["volume-3d"] = [_r(a["simplex_minus_grid_db"], 3), _r(a["simplex_equal_memory_minus_grid_db"], 3)]
+    if acc:
+        acc["cols"] = ["simplex_minus_grid_db", "equal_memory_minus_grid_db"]
+        line["accuracy"] = acc
+    sv = d.get("serving")
+    if sv:
+        line["serving"] = {"saturation_points_per_s": _r(sv["saturation_points_per_s"]),
+                           "loads": [[l["load"], _r(l["p50_ms"], 3), _r(l["p99_ms"], 3), _r(l["points_per_s"], 3)]
+                                     for l in sv["loads"]],
+                           "cols": ["load", "p50_ms", "p99_ms", "points_per_s"]}
+    line["detail"] = detail_path
+    return line
 
 
 if __name__ == "__main__":

@@ -249,6 +249,25 @@ spx_status spx_encode_input_grad(const spx_encoding* enc, int64_t N, const float
 spx_status spx_encode_gather_twin(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
                                   void* out, hipStream_t stream);
 
+/*
+ * Random-gather probe: a measurement reference, not part of the method.
+ * Each of n_threads threads gathers per_thread 4-byte words of `table` at
+ * independent, uniformly random word offsets in [0, n_words) (a
+ * counter-based hash of seed, thread and k; 16 loads in flight per
+ * thread) and writes their 32-bit integer sum to out[thread].  The rate
+ * at a buffer size is the memory system's random-access gather rate for
+ * that footprint (cache level), the ceiling against which the encoding's
+ * gathers, whose rows of one level are hashed uniformly over that level's
+ * table (Sec. 5 steps (a)-(b)), are reported.
+ *   table       device, 4-byte aligned, n_words words (n_words a power of
+ *               two, 1..2^32).
+ *   n_threads   0..2^30.
+ *   per_thread  a multiple of 16 in 16..4096.
+ *   out         device [n_threads] uint32, 4-byte aligned, overwritten.
+ */
+spx_status spx_gather_probe(const void* table, int64_t n_words, int64_t n_threads, int32_t per_thread,
+                            uint32_t seed, uint32_t* out, hipStream_t stream);
+
 /* Round-to-nearest-even binary32 -> binary16 copy of n elements (device,
  * src 4-byte and dst 2-byte aligned). */
 spx_status spx_cast_f32_f16(int64_t n, const float* src, uint16_t* dst, hipStream_t stream);

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libspx.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPX_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "mlp.hip", "optim.hip", "field_query.hip", "composite.hip"]
+SOURCES = ["api.hip", "mlp.hip", "optim.hip", "field_query.hip", "composite.hip", "measure.hip"]
 # encode_unit.hip is compiled once per (cell, dimension, features): (object name, defines)
 UNITS = [(f"encode_{'grid' if g else 'simplex'}_d{d}_f{f}",
           [f"-DSPX_UNIT_GRID={g}", f"-DSPX_UNIT_DIM={d}", f"-DSPX_UNIT_F={f}"])

@@ -279,6 +279,21 @@ spx_status spx_encode_gather_twin(const spx_encoding* enc, int64_t N, const floa
     return from_hip(run(enc, c), "spx_encode_gather_twin launch");
 }
 
+spx_status spx_gather_probe(const void* table, int64_t n_words, int64_t n_threads, int32_t per_thread,
+                            uint32_t seed, uint32_t* out, hipStream_t stream) {
+    if (n_words < 1 || n_words > ((int64_t)1 << 32) || (n_words & (n_words - 1)) != 0)
+        return fail(SPX_EINVAL, "n_words=%lld is not a power of two in 1..2^32", (long long)n_words);
+    if (n_threads < 0 || n_threads > ((int64_t)1 << 30))
+        return fail(SPX_EINVAL, "n_threads=%lld outside 0..2^30", (long long)n_threads);
+    if (per_thread < 16 || per_thread > 4096 || per_thread % 16 != 0)
+        return fail(SPX_EINVAL, "per_thread=%d is not a multiple of 16 in 16..4096", per_thread);
+    if (n_threads == 0) return SPX_OK;
+    if (!table || !out) return fail(SPX_EINVAL, "table or out is NULL");
+    if (!aligned(table, 4) || !aligned(out, 4)) return fail(SPX_EALIGN, "table/out not 4-byte aligned");
+    return from_hip(spx::gather_probe(table, n_words, n_threads, per_thread, seed, out, stream),
+                    "spx_gather_probe launch");
+}
+
 spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* bytes) {
     spx_status st = check_encoding(enc);
     if (st) return st;
@@ -523,9 +538,10 @@ spx_status spx_mlp_bwd_workspace(const spx_mlp* mlp, int64_t N, size_t* bytes) {
     return SPX_OK;
 }
 
-spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1, const uint16_t* W2,
-                       const uint16_t* W3, const float* d_y, float* d_x, float* dW1, float* dW2, float* dW3,
-                       void* workspace, size_t workspace_bytes, hipStream_t stream) {
+static spx_status mlp_bwd_checked(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1,
+                                  const uint16_t* W2, const uint16_t* W3, const float* d_y, float* d_x, float* dW1,
+                                  float* dW2, float* dW3, void* workspace, size_t workspace_bytes,
+                                  hipStream_t stream, const char* fn) {
     spx_status st = check_mlp(mlp, N);
     if (st) return st;
     if (!W1 || !W2 || !W3 || !dW1 || !dW2 || !dW3) return fail(SPX_EINVAL, "NULL weight pointer");
@@ -567,7 +583,14 @@ spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const u
     c.dW3 = dW3;
     c.workspace = workspace;
     c.stream = stream;
-    return from_hip(spx::mlp_bwd(c), "spx_mlp_bwd launch");
+    return from_hip(spx::mlp_bwd(c), fn);
+}
+
+spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1, const uint16_t* W2,
+                       const uint16_t* W3, const float* d_y, float* d_x, float* dW1, float* dW2, float* dW3,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    return mlp_bwd_checked(mlp, N, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, workspace, workspace_bytes, stream,
+                           "spx_mlp_bwd launch");
 }
 
 }  // extern "C"

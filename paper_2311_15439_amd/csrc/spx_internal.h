@@ -256,6 +256,8 @@ hipError_t encode_mlp_fwd(const spx_field& f, int64_t N, const float* pts, float
 hipError_t composite_fwd(int64_t R, int S, const float* raw, const float* delta, float* rgba, hipStream_t s);
 hipError_t composite_bwd(int64_t R, int S, const float* raw, const float* delta, const float* d_rgba, float* d_raw,
                          hipStream_t s);
+hipError_t gather_probe(const void* table, int64_t n_words, int64_t n_threads, int per_thread, uint32_t seed,
+                        uint32_t* out, hipStream_t s);
 hipError_t adam_step(int64_t n, float* param, float* grad, float* m, float* v, uint16_t* param_f16, float lr,
                      float beta1, float beta2, float eps, float bc1, float bc2, int zero_grad, hipStream_t s);
 

@@ -72,6 +72,7 @@ _SIGNATURES = {
                                       C.c_float, C.c_float, C.c_int64, _P, C.c_size_t, _P]),
     "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_encode_gather_twin": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
+    "spx_gather_probe": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_uint32, _P, _P]),
     "spx_encode_input_grad": (C.c_int, [_P, C.c_int64, _P, _P, _P, C.c_int32, _P, _P]),
     "spx_encode_mlp_fwd": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "spx_composite_fwd": (C.c_int, [C.c_int64, C.c_int32, _P, _P, _P, _P]),
@@ -322,6 +323,19 @@ def spx_encode_gather_twin(enc: Encoding, pts, tables, out, stream=None) -> None
     _check(lib().spx_encode_gather_twin(enc.ref(), N, _dev(pts, torch.float32, "pts"),
                                         _dev(tables, torch.float16, "tables"), _dev(out, torch.float16, "out"),
                                         _stream(stream)), "spx_encode_gather_twin")
+
+
+def spx_gather_probe(table, n_threads: int, per_thread: int, seed: int, out, stream=None) -> None:
+    """Measurement reference: per_thread uniformly random 4-byte gathers from
+    `table` (a GPU tensor whose size in words is a power of two) per
+    thread, their integer sum written to out [n_threads] int32."""
+    torch = _torch()
+    nbytes = table.numel() * table.element_size()
+    if nbytes % 4 or out.numel() != n_threads:
+        raise ValueError("table must hold whole 4-byte words and out n_threads entries")
+    _check(lib().spx_gather_probe(_dev(table, None, "table"), nbytes // 4, int(n_threads), int(per_thread),
+                                  int(seed) & 0xFFFFFFFF, _dev(out, torch.int32, "out"), _stream(stream)),
+           "spx_gather_probe")
 
 
 def spx_composite_fwd(raw, delta, rgba, stream=None) -> None:
