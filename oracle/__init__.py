@@ -23,6 +23,7 @@ _LIB = os.environ.get("SPX_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 SIMPLEX, GRID = 0, 1
 F32, F16 = 0, 1
+HASHED, SIZED = 0, 1  # table layouts (see spx_oracle.c)
 MAX_DIM, MAX_LEVELS = 6, 32
 
 
@@ -63,7 +64,7 @@ def library_path() -> str:
 class _Enc(C.Structure):
     _fields_ = [("n_dims", C.c_int), ("n_levels", C.c_int), ("log2_T", C.c_int),
                 ("n_feat", C.c_int), ("table_dtype", C.c_int), ("cell", C.c_int),
-                ("res", C.c_int32 * MAX_LEVELS), ("equal_memory", C.c_int)]
+                ("res", C.c_int32 * MAX_LEVELS), ("equal_memory", C.c_int), ("layout", C.c_int)]
 
 
 _lib = None
@@ -89,6 +90,8 @@ def lib():
             ("orc_f64_to_f16", C.c_uint16, [C.c_double]),
             ("orc_round_bf16", C.c_double, [C.c_double]),
             ("orc_encode_debug", None, [P, C.c_int64, P, P, P, P, P, P]),
+            ("orc_table_layout", None, [P, P, P, P]),
+            ("orc_vertex_slot", C.c_uint32, [P, C.c_int, P]),
             ("orc_encode_fwd", None, [P, C.c_int64, P, P, P]),
             ("orc_encode_fwd_absmag", None, [P, C.c_int64, P, P, P]),
             ("orc_encode_bwd", None, [P, C.c_int64, P, P, P, P, P]),
@@ -127,6 +130,7 @@ class Encoding:
     table_dtype: int = F32
     cell: int = SIMPLEX
     equal_memory: bool = False
+    layout: int = HASHED
 
     @property
     def n_levels(self) -> int:
@@ -143,7 +147,15 @@ class Encoding:
         for i, r in enumerate(self.res):
             e.res[i] = int(r)
         e.equal_memory = int(self.equal_memory)
+        e.layout = int(self.layout)
         return e
+
+    @property
+    def table_shape(self):
+        """[L, T, F] for the hashed layout, [all rows, F] for the sized one."""
+        if self.layout == HASHED:
+            return (self.n_levels, 1 << self.log2_T, self.n_feat)
+        return (int(table_layout(self)["offsets"][-1]), self.n_feat)
 
 
 # --- constants ---------------------------------------------------------------
@@ -191,13 +203,32 @@ def _pts(pts, n):
     return a
 
 
+def table_layout(e: Encoding):
+    """Per level: rows, box extent per axis, dense flag; and the row offsets
+    (offsets[l] is level l's first row, offsets[L] all rows)."""
+    L = e.n_levels
+    rows = np.zeros(L, np.int64)
+    ext = np.zeros(L, np.int32)
+    dense = np.zeros(L, np.int32)
+    ce = e._c()
+    lib().orc_table_layout(C.byref(ce), _p(rows), _p(ext), _p(dense))
+    return dict(rows=rows, extent=ext, dense=dense.astype(bool), offsets=np.concatenate([[0], np.cumsum(rows)]))
+
+
+def vertex_slot(e: Encoding, level: int, v) -> int:
+    """Row of lattice vertex v within the level's table."""
+    a = np.ascontiguousarray(v, np.int32)
+    ce = e._c()
+    return int(lib().orc_vertex_slot(C.byref(ce), int(level), _p(a)))
+
+
 def _tables(e: Encoding, tables):
     dt = np.uint16 if e.table_dtype == F16 else np.float32
     t = np.ascontiguousarray(tables)
     if t.dtype == np.float16:
         t = t.view(np.uint16)
     assert t.dtype == dt, (t.dtype, dt)
-    assert t.size == e.n_levels * (1 << e.log2_T) * e.n_feat
+    assert t.size == int(np.prod(e.table_shape))
     return t
 
 
@@ -243,7 +274,7 @@ def encode_bwd(e: Encoding, pts, d_out, with_stats: bool = False):
     x = _pts(pts, e.n_dims)
     d = np.ascontiguousarray(d_out, np.float64)
     assert d.shape == (len(x), e.n_levels * e.n_feat)
-    shape = (e.n_levels, 1 << e.log2_T, e.n_feat)
+    shape = e.table_shape
     g = np.zeros(shape, np.float64)
     absmag = np.zeros(shape, np.float64) if with_stats else None
     count = np.zeros(shape, np.int64) if with_stats else None

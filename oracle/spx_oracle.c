@@ -36,6 +36,8 @@
 #define ORC_GRID 1
 #define ORC_F32 0
 #define ORC_F16 1
+#define ORC_LAYOUT_HASHED 0
+#define ORC_LAYOUT_SIZED 1
 
 /* ------------------------------------------------------------------------ */
 /* Constants.                                                               */
@@ -189,6 +191,7 @@ typedef struct {
     int n_dims, n_levels, log2_T, n_feat, table_dtype, cell;
     int32_t res[ORC_MAX_LEVELS];
     int equal_memory;
+    int layout; /* ORC_LAYOUT_HASHED or ORC_LAYOUT_SIZED */
 } orc_encoding;
 
 /* Skewed coordinate of Eq. 2 in binary32: the coordinate sum is formed left
@@ -199,6 +202,115 @@ static void skew_point_f32(int n, const float* x, float* y) {
     for (int i = 1; i < n; ++i) s = s + x[i];
     float t = s * Fn;
     for (int i = 0; i < n; ++i) y[i] = x[i] + t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Table layout per level (Sec. 5.2, Hash Table Selection).                  */
+/*   HASHED: every level has T = 2^log2_T rows and every vertex is hashed    */
+/*     (the paper's configurations).                                         */
+/*   SIZED: the lattice box a level reaches from the closed unit cube has    */
+/*     B = e^n vertices.  If B <= T the level is stored densely: B rows, the  */
+/*     vertex v at row sum_i (v_i mod e) e^i, a bijection on the box (no     */
+/*     collisions; coordinates outside it wrap).  Otherwise the level is     */
+/*     hashed into the smallest power of two of rows that holds the share of */
+/*     the box a simplex level actually uses, (n+1)^(-(n-1)/2) (the          */
+/*     volume ratio Sec. 5.2 derives; the whole box for the grid), at most T. */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t off[ORC_MAX_LEVELS + 1]; /* first row of each level; off[L] = all rows */
+    int64_t rows[ORC_MAX_LEVELS];
+    int32_t extent[ORC_MAX_LEVELS];
+    int dense[ORC_MAX_LEVELS];
+} orc_layout;
+
+/* Box extent per axis at one level: the far corner (1, ..., 1) of the unit
+ * cube through the binary32 index path gives the largest scaled coordinate
+ * p any point of the closed cube reaches (each step is monotone), so vertex
+ * coordinates lie in [0, floor(p) + 1]. */
+static int32_t box_extent(const orc_encoding* e, float sigma) {
+    float one[ORC_MAX_DIM], y[ORC_MAX_DIM];
+    for (int i = 0; i < e->n_dims; ++i) one[i] = 1.0f;
+    if (e->cell == ORC_GRID) {
+        for (int i = 0; i < e->n_dims; ++i) y[i] = one[i];
+    } else {
+        skew_point_f32(e->n_dims, one, y);
+    }
+    const float p = y[0] * sigma;
+    return (int32_t)floorf(p) + 2;
+}
+
+static void make_layout(const orc_encoding* e, orc_layout* lay) {
+    const int n = e->n_dims;
+    const int64_t T = (int64_t)1 << e->log2_T;
+    float sigma[ORC_MAX_LEVELS];
+    orc_level_scales(n, e->n_levels, e->res, e->cell, e->equal_memory, sigma);
+    lay->off[0] = 0;
+    for (int l = 0; l < e->n_levels; ++l) {
+        const int32_t ext = box_extent(e, sigma[l]);
+        /* B = ext^n, saturated well above any table size */
+        int64_t B = 1;
+        for (int i = 0; i < n && B <= ((int64_t)1 << 40); ++i) B *= ext;
+        int64_t rows = T;
+        int dense = 0;
+        if (e->layout == ORC_LAYOUT_SIZED) {
+            if (B <= T) {
+                rows = B;
+                dense = 1;
+            } else if (B <= ((int64_t)1 << 40)) {
+                /* smallest power of two P with P >= u B, u = (n+1)^(-(n-1)/2):
+                 * for the simplex P^2 (n+1)^(n-1) >= B^2, in integers */
+                unsigned __int128 rhs = (unsigned __int128)B * (unsigned __int128)B;
+                unsigned __int128 k = 1;
+                if (e->cell != ORC_GRID)
+                    for (int i = 0; i < n - 1; ++i) k *= (unsigned __int128)(n + 1);
+                int64_t P = 1;
+                while (P < T && (e->cell == ORC_GRID ? (P < B)
+                                                      : ((unsigned __int128)P * (unsigned __int128)P * k < rhs)))
+                    P <<= 1;
+                rows = P;
+            }
+        }
+        lay->extent[l] = ext;
+        lay->dense[l] = dense;
+        lay->rows[l] = rows;
+        lay->off[l + 1] = lay->off[l] + rows;
+    }
+}
+
+/* Host query: rows, box extent and dense flag of every level. */
+void orc_table_layout(const orc_encoding* e, int64_t* rows, int32_t* extent, int32_t* dense) {
+    orc_layout lay;
+    make_layout(e, &lay);
+    for (int l = 0; l < e->n_levels; ++l) {
+        rows[l] = lay.rows[l];
+        extent[l] = lay.extent[l];
+        dense[l] = lay.dense[l];
+    }
+}
+
+/* Row of vertex v within level l's table. */
+static uint32_t level_slot(const orc_encoding* e, const orc_layout* lay, int l, const int32_t* v) {
+    if (lay->dense[l]) {
+        const int64_t ext = lay->extent[l];
+        int64_t idx = 0, stride = 1;
+        for (int i = 0; i < e->n_dims; ++i) {
+            int64_t c = (int64_t)v[i] % ext;
+            if (c < 0) c += ext;
+            idx += c * stride;
+            stride *= ext;
+        }
+        return (uint32_t)idx;
+    }
+    uint32_t h = 0;
+    for (int i = 0; i < e->n_dims; ++i) h ^= (uint32_t)v[i] * g_primes[i];
+    return h & (uint32_t)(lay->rows[l] - 1);
+}
+
+/* Host query: row of vertex v within level l's table. */
+uint32_t orc_vertex_slot(const orc_encoding* e, int l, const int32_t* v) {
+    orc_layout lay;
+    make_layout(e, &lay);
+    return level_slot(e, &lay, l, v);
 }
 
 /*
@@ -303,6 +415,8 @@ void orc_encode_debug(const orc_encoding* e, int64_t N, const float* pts, int32_
     int n = e->n_dims, L = e->n_levels, V = n_vertices(e);
     float sigma[ORC_MAX_LEVELS];
     orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
+    orc_layout lay;
+    make_layout(e, &lay);
 #pragma omp parallel for schedule(static)
     for (int64_t pt = 0; pt < N; ++pt) {
         const float* x = pts + pt * n;
@@ -317,7 +431,7 @@ void orc_encode_debug(const orc_encoding* e, int64_t N, const float* pts, int32_
             for (int k = 0; k < V; ++k) {
                 if (verts_out)
                     for (int i = 0; i < n; ++i) verts_out[(base + k) * n + i] = verts[k][i];
-                if (idx_out) idx_out[base + k] = orc_hash(verts[k], n, e->log2_T);
+                if (idx_out) idx_out[base + k] = level_slot(e, &lay, l, verts[k]);
                 if (w64_out) w64_out[base + k] = w64[k];
                 if (w32_out) w32_out[base + k] = w32[k];
             }
@@ -331,11 +445,13 @@ void orc_encode_debug(const orc_encoding* e, int64_t N, const float* pts, int32_
  * Forward encoding (Sec. 5 steps (a)-(d)): for every level, hash the
  * vertices, look up their feature vectors in that level's table, take the
  * barycentric-weighted sum, and concatenate the levels.
- * tables: [L, 2^log2_T, F] in binary32 or binary16; out: [N, L*F] binary64.
+ * tables: [rows of all levels, F] (level l from its layout offset; [L, 2^log2_T, F]
+ * for the hashed layout) in binary32 or binary16; out: [N, L*F] binary64.
  */
 void orc_encode_fwd(const orc_encoding* e, int64_t N, const float* pts, const void* tables, double* out) {
     int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
-    size_t T = (size_t)1 << e->log2_T;
+    orc_layout lay;
+    make_layout(e, &lay);
     float sigma[ORC_MAX_LEVELS];
     orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
 #pragma omp parallel for schedule(static)
@@ -351,8 +467,8 @@ void orc_encode_fwd(const orc_encoding* e, int64_t N, const float* pts, const vo
             for (int j = 0; j < F; ++j) {
                 double acc = 0.0;
                 for (int k = 0; k < V; ++k) {
-                    uint32_t h = orc_hash(verts[k], n, e->log2_T);
-                    acc += w64[k] * table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j);
+                    const size_t row = (size_t)lay.off[l] + level_slot(e, &lay, l, verts[k]);
+                    acc += w64[k] * table_value(tables, e->table_dtype, row * F + j);
                 }
                 out[(size_t)pt * L * F + (size_t)l * F + j] = acc;
             }
@@ -367,7 +483,8 @@ void orc_encode_fwd(const orc_encoding* e, int64_t N, const float* pts, const vo
 void orc_encode_fwd_absmag(const orc_encoding* e, int64_t N, const float* pts, const void* tables,
                            double* out) {
     int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
-    size_t T = (size_t)1 << e->log2_T;
+    orc_layout lay;
+    make_layout(e, &lay);
     float sigma[ORC_MAX_LEVELS];
     orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
 #pragma omp parallel for schedule(static)
@@ -383,8 +500,8 @@ void orc_encode_fwd_absmag(const orc_encoding* e, int64_t N, const float* pts, c
             for (int j = 0; j < F; ++j) {
                 double acc = 0.0;
                 for (int k = 0; k < V; ++k) {
-                    uint32_t h = orc_hash(verts[k], n, e->log2_T);
-                    acc += fabs(w64[k] * table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j));
+                    const size_t row = (size_t)lay.off[l] + level_slot(e, &lay, l, verts[k]);
+                    acc += fabs(w64[k] * table_value(tables, e->table_dtype, row * F + j));
                 }
                 out[(size_t)pt * L * F + (size_t)l * F + j] = acc;
             }
@@ -395,7 +512,7 @@ void orc_encode_fwd_absmag(const orc_encoding* e, int64_t N, const float* pts, c
 /*
  * Adjoint of the forward encoding (Sec. 5 step (e)): the gradient of each
  * output is accumulated into the looked-up feature vectors with the same
- * barycentric weights.  d_out: [N, L*F] binary64; d_tables: [L, T, F]
+ * barycentric weights.  d_out: [N, L*F] binary64; d_tables: laid out as the tables
  * binary64, accumulated (+=).  Serial on purpose: the summation order is the
  * plain point order.  If absmag is non-NULL it receives sum |w * d_out| per
  * slot (same shape as d_tables, accumulated) and count the number of
@@ -404,7 +521,8 @@ void orc_encode_fwd_absmag(const orc_encoding* e, int64_t N, const float* pts, c
 void orc_encode_bwd(const orc_encoding* e, int64_t N, const float* pts, const double* d_out,
                     double* d_tables, double* absmag, int64_t* count) {
     int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
-    size_t T = (size_t)1 << e->log2_T;
+    orc_layout lay;
+    make_layout(e, &lay);
     float sigma[ORC_MAX_LEVELS];
     orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
     for (int64_t pt = 0; pt < N; ++pt) {
@@ -417,9 +535,9 @@ void orc_encode_bwd(const orc_encoding* e, int64_t N, const float* pts, const do
             float w32[1 << ORC_MAX_DIM];
             lookup(e, x, y, sigma[l], verts, w64, w32, NULL);
             for (int k = 0; k < V; ++k) {
-                uint32_t h = orc_hash(verts[k], n, e->log2_T);
+                const size_t row = (size_t)lay.off[l] + level_slot(e, &lay, l, verts[k]);
                 for (int j = 0; j < F; ++j) {
-                    size_t slot = ((size_t)l * T + h) * F + j;
+                    size_t slot = row * F + j;
                     double g = d_out[(size_t)pt * L * F + (size_t)l * F + j];
                     d_tables[slot] += w64[k] * g;
                     if (absmag) absmag[slot] += fabs(w64[k] * g);
@@ -451,7 +569,8 @@ void orc_encode_bwd(const orc_encoding* e, int64_t N, const float* pts, const do
 void orc_encode_input_grad(const orc_encoding* e, int64_t N, const float* pts, const void* tables,
                            const double* d_out, double* d_pts, double* mag) {
     int n = e->n_dims, L = e->n_levels, F = e->n_feat, V = n_vertices(e);
-    size_t T = (size_t)1 << e->log2_T;
+    orc_layout lay;
+    make_layout(e, &lay);
     float sigma[ORC_MAX_LEVELS];
     orc_level_scales(n, L, e->res, e->cell, e->equal_memory, sigma);
     const double Fn = orc_skew_factor(n);
@@ -469,8 +588,8 @@ void orc_encode_input_grad(const orc_encoding* e, int64_t N, const float* pts, c
             double g[ORC_MAX_DIM] = {0}, a[ORC_MAX_DIM] = {0}; /* d L / d f_i and its magnitude */
             double t[1 << ORC_MAX_DIM][8];
             for (int k = 0; k < V; ++k) {
-                uint32_t h = orc_hash(verts[k], n, e->log2_T);
-                for (int j = 0; j < F; ++j) t[k][j] = table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j);
+                const size_t row = (size_t)lay.off[l] + level_slot(e, &lay, l, verts[k]);
+                for (int j = 0; j < F; ++j) t[k][j] = table_value(tables, e->table_dtype, row * F + j);
             }
             const double* d = d_out + (size_t)pt * L * F + (size_t)l * F;
             if (e->cell == ORC_GRID) {

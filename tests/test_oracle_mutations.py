@@ -47,8 +47,8 @@ MUTANTS = {
                                          "dtau += dQ[ch] * (Tn * c[ch] + rest);"),
     "composite adjoint activation": ("const double ds = sigmoid(q[0]) * dl;", "const double ds = dl;"),
     # the magnitude outputs every GPU tolerance is scaled by
-    "fwd magnitude drops the weight": ("acc += fabs(w64[k] * table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j));",
-                                       "acc += fabs(table_value(tables, e->table_dtype, ((size_t)l * T + h) * F + j));"),
+    "fwd magnitude drops the weight": ("acc += fabs(w64[k] * table_value(tables, e->table_dtype, row * F + j));",
+                                       "acc += fabs(table_value(tables, e->table_dtype, row * F + j));"),
     "adjoint magnitude drops the weight": ("if (absmag) absmag[slot] += fabs(w64[k] * g);",
                                            "if (absmag) absmag[slot] += fabs(g);"),
     "input grad magnitude skew chain": ("ax[m] += (double)sigma[l] * (a[m] + Fn * as);",
@@ -62,6 +62,13 @@ MUTANTS = {
                                      "if (with_mag) mag_dW3[o * H + i] += fabs(dy[o]);"),
     "mlp bwd exact mode rounds": ("#define OP(v) (mode == ORC_MLP_BF16 ? orc_round_bf16(v) : (v))",
                                   "#define OP(v) (orc_round_bf16(v))"),
+    # the per-level table layout (Sec. 5.2)
+    "dense row stride": ("            stride *= ext;\n", "            stride *= ext + 1;\n"),
+    "dense wrap of negative coordinates": ("            if (c < 0) c += ext;\n", "\n"),
+    "box extent one short": ("    return (int32_t)floorf(p) + 2;", "    return (int32_t)floorf(p) + 1;"),
+    "used share exponent": ("for (int i = 0; i < n - 1; ++i) k *= (unsigned __int128)(n + 1);",
+                            "for (int i = 0; i < n; ++i) k *= (unsigned __int128)(n + 1);"),
+    "sized level offsets": ("        lay->off[l + 1] = lay->off[l] + rows;", "        lay->off[l + 1] = lay->off[l] + T;"),
     "composite magnitude remainder": ("atau += fabs(dQ[ch]) * (Tn * fabs(c[ch]) + fabs(Q[ch]) + fabs(part[ch]));",
                                       "atau += fabs(dQ[ch]) * (Tn * fabs(c[ch]) + fabs(Q[ch]));"),
 }

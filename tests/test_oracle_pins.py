@@ -872,3 +872,147 @@ def test_mlp_bwd_bf16_mode_within_operand_rounding():
         bound = r * 2.0 ** -8 * 1.01 * b["mag_" + k]
         assert (np.abs(a[k] - b[k]) <= bound + 1e-300).all(), k
         assert np.abs(a[k] - b[k]).max() > 0  # the modes do differ
+
+
+# ---------------------------------------------------------------- table layout (Sec. 5.2)
+# The paper's configurations hash every level into T rows (HASHED).  Sec.
+# 5.2 discusses sizing each level's table by the share of the lattice a
+# simplex level actually uses; the SIZED layout stores a level densely when
+# its whole vertex box fits in T rows, and otherwise hashes it into the
+# smallest power of two that holds that share.
+
+SIZED_CASES = [(2, [16, 24, 36, 54], 14, oracle.SIMPLEX), (3, [4, 9, 20, 45, 90], 16, oracle.SIMPLEX),
+               (2, [5, 12, 130, 700], 14, oracle.GRID), (4, [3, 6, 11, 19], 12, oracle.SIMPLEX),
+               (3, [6, 30, 150], 18, oracle.GRID)]
+
+
+def _box(n, ext):
+    return np.array(list(itertools.product(range(ext), repeat=n)), np.int32)
+
+
+def test_hashed_layout_is_every_level_at_T():
+    e = oracle.Encoding(2, [16, 24, 36, 54], 14)
+    lay = oracle.table_layout(e)
+    assert (lay["rows"] == 1 << 14).all() and not lay["dense"].any()
+    np.testing.assert_array_equal(lay["offsets"], np.arange(5) * (1 << 14))
+
+
+@pytest.mark.parametrize("n,res,log2_T,cell", SIZED_CASES)
+def test_dense_rows_are_a_bijection_on_the_box(n, res, log2_T, cell):
+    e = oracle.Encoding(n, res, log2_T, cell=cell, layout=oracle.SIZED)
+    lay = oracle.table_layout(e)
+    assert lay["dense"].any()
+    rng = np.random.default_rng(30)
+    for l in np.flatnonzero(lay["dense"]):
+        ext = int(lay["extent"][l])
+        assert lay["rows"][l] == ext ** n <= 1 << log2_T
+        box = _box(n, ext)
+        slots = np.array([oracle.vertex_slot(e, l, v) for v in box])
+        np.testing.assert_array_equal(np.sort(slots), np.arange(ext ** n))
+        # outside the box the coordinates wrap: the slot stays in range
+        for v in box[rng.choice(len(box), 10)]:
+            shift = rng.integers(-3, 4, n) * ext
+            assert oracle.vertex_slot(e, l, v + shift) == oracle.vertex_slot(e, l, v)
+
+
+@pytest.mark.parametrize("n,res,log2_T,cell", SIZED_CASES)
+def test_box_holds_the_closed_cube_tightly(n, res, log2_T, cell):
+    """Every vertex a point of the closed unit cube touches lies in the box
+    [0, e-1]^n, and the far corner's walk reaches e-1 on every axis."""
+    e = oracle.Encoding(n, res, log2_T, cell=cell, layout=oracle.SIZED)
+    ext = oracle.table_layout(e)["extent"]
+    corners = np.array(list(itertools.product([0.0, 1.0], repeat=n)), np.float32)
+    x = np.concatenate([inputs.uniform_points(20000, n, 31), corners])
+    v = oracle.encode_debug(e, x)["verts"]
+    for l in range(len(res)):
+        assert v[:, l].min() >= 0 and v[:, l].max() <= ext[l] - 1
+        assert (v[-1, l, -1] == ext[l] - 1).all()  # the corner (1, ..., 1) is listed last
+
+
+@pytest.mark.parametrize("row", _golden("utilization.txt"))
+def test_dense_level_touched_share_matches_figure(row):
+    """Through the dense rows: distinct rows touched by sampling the unit
+    cube, over (N+1)^n, are the paper's printed percentages (Sec. 5.2,
+    memory-usage figure, right panel)."""
+    n, N, pct = int(row[0]), int(row[1]), row[2]
+    e = oracle.Encoding(n, [N], 14, layout=oracle.SIZED)
+    assert oracle.table_layout(e)["dense"][0]
+    rows = [np.unique(oracle.encode_debug(e, inputs.uniform_points(1 << 19, n, 1000 + s))["idx"]) for s in range(4)]
+    touched = len(np.unique(np.concatenate(rows)))
+    assert 100.0 * touched / (N + 1) ** n == pytest.approx(pct, abs=1e-4)
+
+
+def test_hashed_level_rows_hold_the_used_share():
+    """A hashed level of the SIZED layout has the smallest power of two of
+    rows that is at least the used share of its box: the printed
+    theoretical percentage (Sec. 5.2, left panel) for the simplex, all of it
+    for the grid; at most T."""
+    share = {int(r[0]): r[1] / 100.0 for r in _golden("theoretical_utilization.txt")}
+    checked = 0
+    for n, res, log2_T, cell in SIZED_CASES + [(2, list(oracle.level_resolutions(16, 1.662476, 16)), 22,
+                                                oracle.SIMPLEX), (5, [4, 8, 16, 32], 14, oracle.SIMPLEX),
+                                               (3, [100, 120, 135], 20, oracle.SIMPLEX),
+                                               (4, [6, 10, 16, 24], 12, oracle.SIMPLEX),
+                                               (6, [3, 5, 8], 12, oracle.SIMPLEX), (2, [300, 700], 16, oracle.GRID)]:
+        e = oracle.Encoding(n, res, log2_T, cell=cell, layout=oracle.SIZED)
+        lay = oracle.table_layout(e)
+        T = 1 << log2_T
+        for l in np.flatnonzero(~lay["dense"]):
+            B = float(lay["extent"][l]) ** n
+            assert B > T
+            need = B * (share[n] if cell == oracle.SIMPLEX else 1.0)
+            R = int(lay["rows"][l])
+            assert R & (R - 1) == 0 and R <= T
+            if R < T:
+                assert R >= need * (1 - 1e-4) and R / 2 < need * (1 + 1e-4), (n, l, R, need)
+                checked += 1
+            else:
+                assert T / 2 < need * (1 + 1e-4)
+    assert checked >= 3
+
+
+@pytest.mark.parametrize("n,res,log2_T,cell", [(2, [16, 24, 36, 54], 14, oracle.SIMPLEX),
+                                               (3, [4, 9, 20], 16, oracle.SIMPLEX),
+                                               (2, [5, 12, 60], 14, oracle.GRID)])
+def test_dense_levels_reproduce_affine_functions(n, res, log2_T, cell):
+    """All levels dense: rows hold an affine function of their vertex, and the
+    encoding returns that function at p exactly (Sec. 4.3), as with an
+    injective hash."""
+    F = 2
+    e = oracle.Encoding(n, res, log2_T, n_feat=F, cell=cell, layout=oracle.SIZED)
+    lay = oracle.table_layout(e)
+    assert lay["dense"].all()
+    rng = np.random.default_rng(32)
+    A, b = np.round(rng.uniform(-1, 1, (F, n)) * 4), np.round(rng.uniform(-1, 1, F) * 4)
+    tab = np.zeros(e.table_shape, np.float32)
+    for l in range(len(res)):
+        box = _box(n, int(lay["extent"][l]))
+        slots = np.array([oracle.vertex_slot(e, l, v) for v in box])
+        tab[lay["offsets"][l] + slots] = box @ A.T + b
+    x = inputs.uniform_points(3000, n, 33)
+    out = oracle.encode_fwd(e, x, tab).reshape(len(x), len(res), F)
+    p = oracle.encode_debug(e, x)["p"].astype(np.float64)
+    np.testing.assert_allclose(out, np.einsum("nli,fi->nlf", p, A) + b, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("cell", [oracle.SIMPLEX, oracle.GRID])
+def test_sized_adjoint_dot_product_and_fd(cell):
+    """Dense and hashed levels side by side: the adjoint is the transpose of
+    the forward, and central differences on touched rows match it."""
+    n, res, log2_T, F = 3, [4, 11, 40], 12, 2
+    e = oracle.Encoding(n, res, log2_T, n_feat=F, cell=cell, layout=oracle.SIZED)
+    lay = oracle.table_layout(e)
+    assert lay["dense"].any() and not lay["dense"].all()
+    x = inputs.uniform_points(700, n, 34)
+    t = inputs.dense_values(e.table_shape, 35).astype(np.float32)
+    d = inputs.gradients(len(x), len(res) * F, 36).astype(np.float64)
+    g = oracle.encode_bwd(e, x, d)
+    assert g.shape == e.table_shape
+    assert (d * oracle.encode_fwd(e, x, t)).sum() == pytest.approx((g * t.astype(np.float64)).sum(), rel=1e-12)
+    for (r, j) in np.argwhere(g != 0)[::97][:6]:
+        tp, tm = t.copy(), t.copy()
+        tp[r, j] += 0.5
+        tm[r, j] -= 0.5
+        step = float(tp[r, j]) - float(tm[r, j])
+        fd = ((d * oracle.encode_fwd(e, x, tp)).sum() - (d * oracle.encode_fwd(e, x, tm)).sum()) / step
+        assert fd == pytest.approx(g[r, j], rel=1e-9, abs=1e-12)
