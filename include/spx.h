@@ -7,7 +7,8 @@
  *   - Pointers documented "device" address GPU memory owned by the caller
  *     (for example torch tensors); pointers documented "host" address CPU
  *     memory read or written during the call only.  The library never
- *     allocates, frees or keeps a pointer after returning.
+ *     allocates, frees or keeps a pointer after returning; its only device
+ *     memory of its own is the static scratch of spx_mlp_bwd_noalloc.
  *   - Calls that take a hipStream_t enqueue their kernels on that stream and
  *     return without waiting.  Argument checks happen on the host before
  *     anything is enqueued; a call that returns an error has enqueued
@@ -371,6 +372,26 @@ spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const u
                        const uint16_t* W2, const uint16_t* W3, const float* d_y, float* d_x, float* dW1,
                        float* dW2, float* dW3, void* workspace, size_t workspace_bytes,
                        hipStream_t stream);
+
+/*
+ * spx_mlp_bwd without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The weight-gradient partials go
+ * to a scratch array that the library holds in static device memory: 14 MiB
+ * per GPU (the partials of the 512 workgroups the backward launches at
+ * most), kept until the process ends.  Its device address is looked up
+ * with hipGetSymbolAddress on the first call on each device; the call
+ * itself allocates nothing.  Every N accepted by spx_mlp_bwd fits
+ * (SPX_EUNSUPPORTED otherwise).  Every partial the reduction reads is
+ * written by the same call, so nothing needs clearing; but all calls on one
+ * GPU share the array, so calls that overlap in time on one GPU (on
+ * different streams, or from different threads without ordering) race and
+ * give wrong gradients: serialise them.  Results are bit-identical to
+ * spx_mlp_bwd.  Other arguments and errors as spx_mlp_bwd.
+ */
+spx_status spx_mlp_bwd_noalloc(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1,
+                               const uint16_t* W2, const uint16_t* W3, const float* d_y, float* d_x, float* dW1,
+                               float* dW2, float* dW3, hipStream_t stream);
 
 /*
  * Serving: several resident fields (encoding + network), queried together.

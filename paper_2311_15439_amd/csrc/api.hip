@@ -593,4 +593,21 @@ spx_status spx_mlp_bwd(const spx_mlp* mlp, int64_t N, const uint16_t* x, const u
                            "spx_mlp_bwd launch");
 }
 
+spx_status spx_mlp_bwd_noalloc(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1,
+                               const uint16_t* W2, const uint16_t* W3, const float* d_y, float* d_x, float* dW1,
+                               float* dW2, float* dW3, hipStream_t stream) {
+    spx_status st = check_mlp(mlp, N);
+    if (st) return st;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    hipError_t he = spx::mlp_bwd_scratch(&scratch, &scratch_bytes);
+    if (he != hipSuccess) return from_hip(he, "scratch lookup (hipGetSymbolAddress)");
+    const size_t need = spx::mlp_bwd_workspace_bytes(mlp->d_in, mlp->hidden, mlp->d_out, N);
+    if (need > scratch_bytes)
+        return fail(SPX_EUNSUPPORTED, "N=%lld needs %zu bytes of scratch, the library holds %zu", (long long)N, need,
+                    scratch_bytes);
+    return mlp_bwd_checked(mlp, N, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, scratch, scratch_bytes, stream,
+                           "spx_mlp_bwd_noalloc launch");
+}
+
 }  // extern "C"

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mfma_mlp.hpp"
 #include "spx_internal.h"
 
@@ -394,6 +396,34 @@ hipError_t bwd_impl(const MlpCall& c) {
 }
 
 }  // namespace
+
+// Scratch of the allocation-free backward (spx_mlp_bwd_noalloc): room for the
+// per-workgroup weight-gradient partials of the most workgroups the backward
+// ever launches (kMaxBwdGroups), 14 MiB per device, held until the process
+// ends.  In host code this name is only a stand-in for the symbol: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchFloats = (size_t)kMaxBwdGroups * BwdLayout<32>::PARTIAL;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+hipError_t mlp_bwd_scratch(void** ptr, size_t* bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *bytes = kScratchFloats * sizeof(float);
+    return hipSuccess;
+}
 
 int mlp_bwd_lds_bytes(int d_in) { return d_in == 32 ? BwdLayout<32>::LDS_BYTES : 0; }
 

@@ -244,6 +244,9 @@ struct MlpCall {
 };
 size_t mlp_bwd_workspace_bytes(int d_in, int hidden, int d_out, int64_t N);
 int mlp_bwd_lds_bytes(int d_in);
+// Device address and size of the current device's scratch for the
+// allocation-free backward (looked up on first use per device).
+hipError_t mlp_bwd_scratch(void** ptr, size_t* bytes);
 hipError_t mlp_fwd(const MlpCall& c);
 hipError_t mlp_bwd(const MlpCall& c);
 

@@ -86,6 +86,7 @@ _SIGNATURES = {
     "spx_mlp_fwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P]),
     "spx_mlp_bwd_workspace": (C.c_int, [_P, C.c_int64, _P]),
     "spx_mlp_bwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "spx_mlp_bwd_noalloc": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
 }
 
 _lib: Optional[C.CDLL] = None
@@ -437,6 +438,23 @@ def spx_mlp_bwd(mlp: spx_mlp, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, workspace,
                              _dev(dW1, f, "dW1"), _dev(dW2, f, "dW2"), _dev(dW3, f, "dW3"),
                              _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)),
            "spx_mlp_bwd")
+
+
+def spx_mlp_bwd_noalloc(mlp: spx_mlp, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, stream=None) -> None:
+    """spx_mlp_bwd with the library's static scratch instead of a workspace
+    (nothing is allocated; calls overlapping on one GPU race)."""
+    torch = _torch()
+    N = x.shape[0]
+    if tuple(d_y.shape) != (N, mlp.d_out):
+        raise ValueError("d_y must be [N, d_out]")
+    if d_x is not None and tuple(d_x.shape) != (N, mlp.d_in):
+        raise ValueError("d_x must be [N, d_in]")
+    h, f = torch.float16, torch.float32
+    _check(lib().spx_mlp_bwd_noalloc(C.byref(mlp), N, _dev(x, h, "x"), _dev(W1, h, "W1"), _dev(W2, h, "W2"),
+                                     _dev(W3, h, "W3"), _dev(d_y, f, "d_y"),
+                                     None if d_x is None else _dev(d_x, f, "d_x"), _dev(dW1, f, "dW1"),
+                                     _dev(dW2, f, "dW2"), _dev(dW3, f, "dW3"), _stream(stream)),
+           "spx_mlp_bwd_noalloc")
 
 
 # --------------------------------------------------------------- serving
