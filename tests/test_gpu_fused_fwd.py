@@ -43,3 +43,41 @@ def test_fused_forward_rejects_other_shapes():
     with pytest.raises(spx.SpxError):
         spx.spx_encode_mlp_fwd(enc, mlp, torch.zeros((4, 2), device="cuda"), tab, *W,
                                torch.zeros((4, 3), device="cuda"))
+
+
+@pytest.mark.parametrize("n,cell", [(2, spx.SPX_SIMPLEX), (2, spx.SPX_GRID), (3, spx.SPX_SIMPLEX),
+                                    (3, spx.SPX_GRID)])
+def test_fused_forward_matches_oracle_full_size(n, cell):
+    """The workloads' shapes (image: n=2, T=2^22, levels 16..32768; volume:
+    n=3, T=2^19, levels 16..2048, ray-major samples), 2^20 points through
+    the fused kernel; features and outputs of 4096 sampled points against
+    the oracle: features within 1e-5 of their magnitude plus the binary16
+    rounding of the output, outputs against the oracle's network on the
+    features the kernel encoded (tests/tolerances.py)."""
+    import oracle
+    from tolerances import mlp_fwd_problem
+    w = inputs.IMAGE_2D if n == 2 else inputs.VOLUME_3D
+    N = 1 << 20
+    res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
+    enc = spx.Encoding(n, res, w.log2_T, 2, table_dtype=spx.SPX_F16, cell=cell)
+    d_out = 3 if n == 2 else 4
+    mlp = spx.make_mlp(32, 64, d_out)
+    host_tab = inputs.tables(16, 1 << w.log2_T, 2, 0.5, 70 + n, True)
+    Wh = inputs.mlp_weights(32, 64, d_out, 71)
+    pts = inputs.pixel_points(N, 72) if n == 2 else inputs.ray_points(N // 256, 256, 72)
+    tab = torch.from_numpy(host_tab).cuda()
+    W = [torch.from_numpy(a).cuda() for a in Wh]
+    feats = torch.empty((N, 32), dtype=torch.float16, device="cuda")
+    y = torch.empty((N, d_out), dtype=torch.float32, device="cuda")
+    spx.spx_encode_mlp_fwd(enc, mlp, torch.from_numpy(pts).cuda(), tab, *W, y, feats=feats)
+    torch.cuda.synchronize()
+    sel = np.sort(np.random.default_rng(73).choice(N, 4096, replace=False))
+    f = feats.cpu().numpy()[sel]
+    oe = oracle.Encoding(n, list(res), w.log2_T, 2, table_dtype=oracle.F16, cell=cell)
+    ref = oracle.encode_fwd(oe, pts[sel], host_tab)
+    mag = oracle.encode_fwd_absmag(oe, pts[sel], host_tab)
+    err = np.abs(f.astype(np.float64) - ref)
+    assert (err <= 1e-5 * mag + 2.0 ** -11 * np.abs(ref) + 2.0 ** -25).all(), err.max()
+    yo, ym = oracle.mlp_fwd(f, *Wh, with_absmag=True)
+    p = mlp_fwd_problem(y.cpu().numpy()[sel], yo, ym)
+    assert p is None, p

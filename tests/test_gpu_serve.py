@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 from paper_2311_15439_amd import inputs, spx
+from tolerances import mlp_fwd_problem
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -64,9 +65,16 @@ def test_field_query_equals_separate_kernels():
     f, pts, out = bufs[4]
     fd = fields[f]
     oe = oracle.Encoding(fd["enc"].n_dims, list(fd["enc"].res), 14, 2, table_dtype=oracle.F16, cell=fd["enc"].cell)
-    feats = oracle.encode_fwd(oe, pts.cpu().numpy(), fd["tab"].cpu().numpy()).astype(np.float16)
-    yo, ym = oracle.mlp_fwd(feats, *[w.cpu().numpy() for w in fd["W"]], with_absmag=True)
-    assert (np.abs(out.cpu().numpy() - yo) <= 2.0 ** -9 * ym + 2.0 ** -10 * np.abs(yo) + 1e-6).all()
+    gfeats = torch.empty((len(pts), 32), dtype=torch.float16, device=DEV)
+    spx.spx_encode_fwd(fd["enc"], pts, fd["tab"], gfeats)
+    gfeats = gfeats.cpu().numpy()
+    p_np, tab_np = pts.cpu().numpy(), fd["tab"].cpu().numpy()
+    fo, fm = oracle.encode_fwd(oe, p_np, tab_np), oracle.encode_fwd_absmag(oe, p_np, tab_np)
+    assert (np.abs(gfeats.astype(np.float64) - fo) <= 1e-5 * fm + 2.0 ** -11 * np.abs(fo) + 2.0 ** -25).all()
+    # the network on the features the kernel encoded (binary16, as it feeds them to the matrix cores)
+    yo, ym = oracle.mlp_fwd(gfeats, *[w.cpu().numpy() for w in fd["W"]], with_absmag=True)
+    p = mlp_fwd_problem(out.cpu().numpy(), yo, ym)
+    assert p is None, p
 
 
 def test_server_alone_equals_mixed_on_gpu():
