@@ -210,8 +210,8 @@ static void skew_point_f32(int n, const float* x, float* y) {
 /*     (the paper's configurations).                                         */
 /*   SIZED: the lattice box a level reaches from the closed unit cube has    */
 /*     B = e^n vertices.  If B <= T the level is stored densely: B rows, the  */
-/*     vertex v at row sum_i (v_i mod e) e^i, a bijection on the box (no     */
-/*     collisions; coordinates outside it wrap).  Otherwise the level is     */
+/*     vertex v at row sum_i v_i e^i, a bijection on the box (no collisions;  */
+/*     coordinates outside it are clamped to its faces).  Otherwise it is    */
 /*     hashed into the smallest power of two of rows that holds the share of */
 /*     the box a simplex level actually uses, (n+1)^(-(n-1)/2) (the          */
 /*     volume ratio Sec. 5.2 derives; the whole box for the grid), at most T. */
@@ -294,8 +294,9 @@ static uint32_t level_slot(const orc_encoding* e, const orc_layout* lay, int l, 
         const int64_t ext = lay->extent[l];
         int64_t idx = 0, stride = 1;
         for (int i = 0; i < e->n_dims; ++i) {
-            int64_t c = (int64_t)v[i] % ext;
-            if (c < 0) c += ext;
+            int64_t c = v[i];
+            if (c < 0) c = 0;
+            if (c > ext - 1) c = ext - 1;
             idx += c * stride;
             stride *= ext;
         }

@@ -64,7 +64,8 @@ MUTANTS = {
                                   "#define OP(v) (orc_round_bf16(v))"),
     # the per-level table layout (Sec. 5.2)
     "dense row stride": ("            stride *= ext;\n", "            stride *= ext + 1;\n"),
-    "dense wrap of negative coordinates": ("            if (c < 0) c += ext;\n", "\n"),
+    "dense clamp of negative coordinates": ("            if (c < 0) c = 0;\n", "\n"),
+    "dense clamp of the upper face": ("            if (c > ext - 1) c = ext - 1;\n", "            if (c > ext) c = ext;\n"),
     "box extent one short": ("    return (int32_t)floorf(p) + 2;", "    return (int32_t)floorf(p) + 1;"),
     "used share exponent": ("for (int i = 0; i < n - 1; ++i) k *= (unsigned __int128)(n + 1);",
                             "for (int i = 0; i < n; ++i) k *= (unsigned __int128)(n + 1);"),
