@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define SPX_ABI_VERSION 1
+#define SPX_ABI_VERSION 2
 #define SPX_MAX_DIMS 6
 #define SPX_MAX_LEVELS 32
 #define SPX_MAX_LOG2_T 26
@@ -47,6 +47,7 @@ typedef enum {
 
 enum { SPX_F32 = 0, SPX_F16 = 1 };
 enum { SPX_SIMPLEX = 0, SPX_GRID = 1 };
+enum { SPX_LAYOUT_HASHED = 0, SPX_LAYOUT_SIZED = 1 };
 
 /*
  * Encoding descriptor (host memory, read during the call only).
@@ -62,8 +63,24 @@ enum { SPX_SIMPLEX = 0, SPX_GRID = 1 };
  *                simplex and grid at the same table size (Sec. 5.2).
  *                Ignored for SPX_GRID.
  *   res[l]       N_l >= 1, the resolution of level l (l < n_levels).
- * Tables are laid out [L][T][F] (level-major, feature innermost) and the
- * encoded features [N][L*F] (levels concatenated in order, Sec. 5 step (d)).
+ *   layout       how each level's vertices map to table rows (Sec. 5.2,
+ *                Hash Table Selection):
+ *                SPX_LAYOUT_HASHED: every level has T rows and every vertex
+ *                  is hashed (the paper's configurations);
+ *                SPX_LAYOUT_SIZED: the box of vertices the closed unit cube
+ *                  reaches at level l has ext_l^n vertices (ext_l from
+ *                  spx_table_layout).  If that is at most T, the level is
+ *                  stored densely: ext_l^n rows, vertex v at row
+ *                  sum_i v_i ext_l^i (no collisions; the coordinates of
+ *                  points outside the cube are clamped to the box).
+ *                  Otherwise it is hashed into the
+ *                  smallest power of two of rows that holds the share of
+ *                  the box a simplex level uses, (n+1)^(-(n-1)/2) (all of it
+ *                  for the grid), at most T.
+ * Tables are laid out level after level, feature innermost: level l's rows
+ * start at row offset_l = rows_0 + ... + rows_{l-1} (spx_table_layout); for
+ * SPX_LAYOUT_HASHED that is [L][T][F].  The encoded features are [N][L*F]
+ * (levels concatenated in order, Sec. 5 step (d)).
  */
 typedef struct {
     int32_t n_dims;
@@ -74,6 +91,7 @@ typedef struct {
     int32_t cell;
     int32_t equal_memory;
     int32_t res[SPX_MAX_LEVELS];
+    int32_t layout;
 } spx_encoding;
 
 /* ABI version compiled into the library (SPX_ABI_VERSION). */
@@ -126,6 +144,18 @@ spx_status spx_level_resolutions(double n_min, double growth, int32_t L, int32_t
 spx_status spx_level_scales(const spx_encoding* enc, float* sigma_out);
 
 /*
+ * Host helper: the table layout of an encoding (Sec. 5.2).  Per level
+ * (host arrays of n_levels entries, each may be NULL): level_rows, the rows
+ * of its table; box_extent, the extent per axis of the vertex box the
+ * closed unit cube reaches (the far corner (1,...,1) skewed and scaled in
+ * binary32, floored, plus 2); dense, 1 if the level is stored densely.
+ * *total_rows (may be NULL): rows of all levels; the tables hold
+ * total_rows * n_feat values.
+ */
+spx_status spx_table_layout(const spx_encoding* enc, int64_t* level_rows, int32_t* box_extent, int32_t* dense,
+                            int64_t* total_rows);
+
+/*
  * Host helper: the six hash multipliers P_0..P_5.  A vertex v of level l is
  * stored at slot (XOR_i uint32(v_i) * P_i mod 2^32) & (T - 1) of that
  * level's table (Sec. 5 steps (a)-(b); the paper does not print its hash).
@@ -143,8 +173,9 @@ spx_status spx_hash_primes(uint32_t* primes_out);
  *   pts      device [N][n] binary32, 4-byte aligned.  Any finite value is
  *            legal (the hash is total); positions are exact for
  *            |sigma_l * skewed coordinate| < 2^24.
- *   tables   device [L][T][F] of enc->table_dtype, aligned to one row
- *            (F * element size, at most 16 bytes).
+ *   tables   device, the table layout's rows (spx_table_layout) of F
+ *            values of enc->table_dtype, aligned to one row (F * element
+ *            size, at most 16 bytes).
  *   out      device [N][L*F] of out_dtype (SPX_F32 or SPX_F16), aligned to
  *            F * element size (at most 16 bytes).  Overwritten.
  * Deterministic: the same inputs give bit-identical outputs.
@@ -158,7 +189,7 @@ spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, 
  * weights and slots.  There is no gradient with respect to the points.
  *   d_out      device [N][L*F] of d_out_dtype (SPX_F32 or SPX_F16), aligned
  *              to F * element size (at most 16 bytes).
- *   d_tables   device [L][T][F] binary32, 4-byte aligned.  ACCUMULATED: the
+ *   d_tables   device binary32, laid out as the tables, 4-byte aligned.  ACCUMULATED: the
  *              caller zeroes it.  The summation order, and so the last bits,
  *              vary from run to run.
  *   workspace  NULL: every contribution is added with a binary32 atomic.
@@ -188,11 +219,12 @@ spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* 
  * Adam step of spx_adam_step is applied to every entry of the tables at
  * once, so no gradient table is written or read.  Every entry is updated
  * (entries with zero gradient still decay m and v), exactly as
- * spx_encode_bwd into zeros followed by spx_adam_step over all L*T*F
+ * spx_encode_bwd into zeros followed by spx_adam_step over all total_rows*F
  * entries.
- *   param, m, v  device [L][T][F] binary32, 16-byte aligned: master tables
- *                and Adam moments, updated in place.
- *   param_f16    device [L][T][F] binary16, 8-byte aligned, or NULL: receives
+ *   param, m, v  device binary32 laid out as the tables, 16-byte aligned:
+ *                master tables and Adam moments, updated in place.
+ *   param_f16    device binary16 laid out as the tables, 8-byte aligned, or
+ *                NULL: receives
  *                the binary16 image of the updated tables (the forward's
  *                input).
  *   lr, beta1, beta2, eps, step   as spx_adam_step.
@@ -242,7 +274,7 @@ spx_status spx_encode_input_grad(const spx_encoding* enc, int64_t N, const float
  * memory system sustains on the forward's access pattern; the forward's
  * rate divided by it is the forward's fraction of that gather roofline.
  *   tables  device [L][T][2] binary16 (n_feat must be 2, table_dtype
- *           SPX_F16), 4-byte aligned.
+ *           SPX_F16, layout SPX_LAYOUT_HASHED), 4-byte aligned.
  *   out     device [N][L*2] binary16, 4-byte aligned: per level, the
  *           unweighted sum of the gathered rows.
  * Other feature counts or table types return SPX_EUNSUPPORTED.
@@ -436,7 +468,8 @@ typedef struct {
 
 /*
  * Host helper: validate a field and fill *out (host memory).  enc must be a
- * 2- or 3-D encoding with 16 levels, 2 features and binary16 tables.
+ * 2- or 3-D encoding with 16 levels, 2 features and binary16 tables in the
+ * hashed layout (SPX_EUNSUPPORTED otherwise).
  */
 spx_status spx_field_init(const spx_encoding* enc, const void* tables, const uint16_t* W1, const uint16_t* W2,
                           const uint16_t* W3, int32_t d_out, spx_field* out);

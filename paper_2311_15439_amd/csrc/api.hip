@@ -108,6 +108,8 @@ spx_status check_encoding(const spx_encoding* e) {
         return fail(SPX_EINVAL, "table_dtype=%d is not SPX_F32 or SPX_F16", e->table_dtype);
     if (e->cell != SPX_SIMPLEX && e->cell != SPX_GRID) return fail(SPX_EINVAL, "cell=%d unknown", e->cell);
     if (e->equal_memory != 0 && e->equal_memory != 1) return fail(SPX_EINVAL, "equal_memory must be 0 or 1");
+    if (e->layout != SPX_LAYOUT_HASHED && e->layout != SPX_LAYOUT_SIZED)
+        return fail(SPX_EINVAL, "layout=%d is not SPX_LAYOUT_HASHED or SPX_LAYOUT_SIZED", e->layout);
     for (int l = 0; l < e->n_levels; ++l)
         if (e->res[l] < 1) return fail(SPX_EINVAL, "res[%d]=%d < 1", l, e->res[l]);
     return SPX_OK;
@@ -127,15 +129,73 @@ void level_scales(const spx_encoding* e, float* sigma) {
     }
 }
 
+// Box extent per axis at one level: the far corner (1, ..., 1) of the unit
+// cube through the binary32 index path (skew, then scale) gives the largest
+// scaled coordinate of any point of the closed cube, so its vertices lie in
+// [0, floor(p) + 1].
+int32_t box_extent(const spx_encoding* e, float sigma, float Fn) {
+#pragma clang fp contract(off)
+    float y = 1.0f;
+    if (e->cell == SPX_SIMPLEX) {
+        float s = 1.0f;
+        for (int i = 1; i < e->n_dims; ++i) s = s + 1.0f;
+        const float t = s * Fn;
+        y = 1.0f + t;
+    }
+    const float p = y * sigma;
+    return (int32_t)floorf(p) + 2;
+}
+
+// Rows of each level (Sec. 5.2, Hash Table Selection): SPX_LAYOUT_HASHED
+// gives every level T rows; SPX_LAYOUT_SIZED stores a level densely when
+// its ext^n box fits in T rows, and otherwise gives it the smallest power of
+// two P >= u ext^n, u = (n+1)^(-(n-1)/2) for the simplex (1 for the grid),
+// at most T; for the simplex the test is P^2 (n+1)^(n-1) >= (ext^n)^2 in
+// integers.
+void level_layout(const spx_encoding* e, spx::LevelArgs& lv) {
+    const int n = e->n_dims;
+    const uint64_t T = 1ull << e->log2_T;
+    uint64_t off = 0;
+    lv.dense = 0;
+    for (int l = 0; l < e->n_levels; ++l) {
+        const int32_t ext = box_extent(e, lv.sigma[l], lv.Fn);
+        uint64_t B = 1;
+        for (int i = 0; i < n && B <= (1ull << 40); ++i) B *= (uint64_t)ext;
+        uint64_t rows = T;
+        if (e->layout == SPX_LAYOUT_SIZED) {
+            if (B <= T) {
+                rows = B;
+                lv.dense |= 1u << l;
+            } else if (B <= (1ull << 40)) {
+                unsigned __int128 k = 1;
+                if (e->cell == SPX_SIMPLEX)
+                    for (int i = 0; i + 1 < n; ++i) k *= (unsigned)(n + 1);
+                const unsigned __int128 B2 = (unsigned __int128)B * B;
+                uint64_t P = 1;
+                while (P < T) {
+                    const bool enough = e->cell == SPX_SIMPLEX ? (unsigned __int128)P * P * k >= B2 : P >= B;
+                    if (enough) break;
+                    P <<= 1;
+                }
+                rows = P;
+            }
+        }
+        lv.ext[l] = ext;
+        lv.rows[l] = (uint32_t)rows;
+        lv.off[l] = off;
+        off += rows;
+    }
+}
+
 spx::LevelArgs level_args(const spx_encoding* e) {
     spx::LevelArgs lv;
     memset(&lv, 0, sizeof(lv));
     level_scales(e, lv.sigma);
     const int n = e->n_dims;
     lv.Fn = (float)((sqrt((double)n + 1.0) - 1.0) / (double)n);
-    lv.reach = e->cell == SPX_SIMPLEX ? (float)sqrt((double)n + 1.0) : 1.0f;
     lv.mask = (uint32_t)((1ull << e->log2_T) - 1ull);
     lv.L = e->n_levels;
+    level_layout(e, lv);
     return lv;
 }
 
@@ -154,8 +214,7 @@ spx::EncodeCall base_call(const spx_encoding* e, int64_t N, const float* pts, hi
 
 spx::BinLayout layout_for(const spx_encoding* e, int64_t N) {
     const spx::LevelArgs lv = level_args(e);
-    return spx::bin_layout(e->n_dims, e->n_feat, e->n_levels, e->log2_T, N, e->cell == SPX_SIMPLEX, lv.sigma,
-                           (double)lv.reach);
+    return spx::bin_layout(e->n_dims, e->n_feat, N, e->cell == SPX_SIMPLEX, lv);
 }
 
 hipError_t run(const spx_encoding* e, const spx::EncodeCall& c) {
@@ -215,6 +274,22 @@ spx_status spx_level_scales(const spx_encoding* enc, float* sigma_out) {
     return SPX_OK;
 }
 
+spx_status spx_table_layout(const spx_encoding* enc, int64_t* level_rows, int32_t* box_extent_out,
+                            int32_t* dense_out, int64_t* total_rows) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    const spx::LevelArgs lv = level_args(enc);
+    int64_t total = 0;
+    for (int l = 0; l < enc->n_levels; ++l) {
+        if (level_rows) level_rows[l] = (int64_t)lv.rows[l];
+        if (box_extent_out) box_extent_out[l] = lv.ext[l];
+        if (dense_out) dense_out[l] = (int32_t)((lv.dense >> l) & 1u);
+        total += (int64_t)lv.rows[l];
+    }
+    if (total_rows) *total_rows = total;
+    return SPX_OK;
+}
+
 spx_status spx_hash_primes(uint32_t* primes_out) {
     if (!primes_out) return fail(SPX_EINVAL, "primes_out is NULL");
     for (int i = 0; i < SPX_MAX_DIMS; ++i) primes_out[i] = spx::hash_prime(i);
@@ -266,8 +341,8 @@ spx_status spx_encode_gather_twin(const spx_encoding* enc, int64_t N, const floa
     spx_status st = check_encoding(enc);
     if (st) return st;
     if ((st = check_points(N, pts))) return st;
-    if (enc->n_feat != 2 || enc->table_dtype != SPX_F16)
-        return fail(SPX_EUNSUPPORTED, "the gather twin covers binary16 tables with n_feat = 2");
+    if (enc->n_feat != 2 || enc->table_dtype != SPX_F16 || enc->layout != SPX_LAYOUT_HASHED)
+        return fail(SPX_EUNSUPPORTED, "the gather twin covers hashed binary16 tables with n_feat = 2");
     if (N == 0) return SPX_OK;
     if (!tables || !out) return fail(SPX_EINVAL, "tables or out is NULL");
     if (!aligned(tables, 4) || !aligned(out, 4)) return fail(SPX_EALIGN, "tables/out not 4-byte aligned");
@@ -454,6 +529,8 @@ spx_status spx_field_init(const spx_encoding* enc, const void* tables, const uin
     if (enc->n_dims != 2 && enc->n_dims != 3) return fail(SPX_EUNSUPPORTED, "fields are 2- or 3-D (n_dims=%d)", enc->n_dims);
     if (enc->n_levels != 16 || enc->n_feat != 2 || enc->table_dtype != SPX_F16)
         return fail(SPX_EUNSUPPORTED, "fields use 16 levels of 2 binary16 features");
+    if (enc->layout != SPX_LAYOUT_HASHED)
+        return fail(SPX_EUNSUPPORTED, "fields use the hashed table layout");
     if (d_out < 1 || d_out > 16) return fail(SPX_EINVAL, "d_out=%d outside 1..16", d_out);
     if (!tables || !W1 || !W2 || !W3) return fail(SPX_EINVAL, "NULL table or weight pointer");
     if (!aligned(tables, 4) || !aligned(W1, 16) || !aligned(W2, 16) || !aligned(W3, 16))

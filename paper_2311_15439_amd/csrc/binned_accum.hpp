@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include "encode_kernels.hpp"
+#include "wave_runs.hpp"
 
 namespace spx {
 
@@ -37,6 +38,30 @@ __device__ __forceinline__ void lds_add(float* p, float v) {
                                                    __HIP_MEMORY_SCOPE_WORKGROUP));
 }
 
+// Adds a row of F floats.  Pairs of floats go through one 64-bit
+// compare-and-swap (the LDS takes about as long for it as for a 32-bit one,
+// so a two-feature row costs one retry loop instead of two); each float
+// is still the plain binary32 sum of the old value and the addend.
+template <int F>
+__device__ __forceinline__ void lds_add_row(float* row, const float (&v)[F]) {
+    if constexpr (F == 1) {
+        lds_add(row, v[0]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < F; j += 2) {
+            uint64_t* q = reinterpret_cast<uint64_t*>(row + j);
+            uint64_t seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            uint64_t want;
+            do {
+                const float lo = __uint_as_float((uint32_t)seen) + v[j];
+                const float hi = __uint_as_float((uint32_t)(seen >> 32)) + v[j + 1];
+                want = (uint64_t)__float_as_uint(lo) | ((uint64_t)__float_as_uint(hi) << 32);
+            } while (!__hip_atomic_compare_exchange_strong(q, &seen, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP));
+        }
+    }
+}
+
 constexpr int kAccBlock = 1024;  // one workgroup per CU (128 KiB accumulator)
 constexpr int kAccUnroll = 2;
 
@@ -62,37 +87,18 @@ __device__ __forceinline__ void adam4(const AdamArgs& a, f32x4 g, f32x4& p, f32x
 // the same terms in a different order.  Every lane of the wave must call it.
 template <int F>
 __device__ __forceinline__ void lds_add_wave(float* acc, bool ok, uint32_t slot, const float (&val)[F]) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t key = ok ? slot : 0xFFFFFFFFu;
-    const uint32_t prev = __shfl_up(key, 1, 64);
-    const bool joins = ok && lane > 0 && prev == key;
-    if (__ballot(joins) == 0) {
-        if (ok)
-#pragma unroll
-            for (int j = 0; j < F; ++j) lds_add(&acc[slot * F + j], val[j]);
+    const uint32_t key = ok ? slot : kNoKey;
+    const bool joins = joins_prev(key);
+    const uint64_t heads = __ballot(!joins);
+    if (heads == ~0ull) {
+        if (ok) lds_add_row<F>(&acc[slot * F], val);
         return;
-    }
-    int start = joins ? 0 : lane;  // first lane of this lane's run
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(start, off, 64);
-        if (lane >= off && t > start) start = t;
     }
     float v[F];
 #pragma unroll
-    for (int j = 0; j < F; ++j) v[j] = ok ? val[j] : 0.0f;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-        for (int j = 0; j < F; ++j) {
-            const float t = __shfl_up(v[j], off, 64);
-            if (lane - off >= start) v[j] += t;
-        }
-    }
-    const int next_joins = __shfl_down((int)joins, 1, 64);
-    if (ok && (lane == 63 || !next_joins))
-#pragma unroll
-        for (int j = 0; j < F; ++j) lds_add(&acc[slot * F + j], v[j]);
+    for (int j = 0; j < F; ++j) v[j] = val[j];
+    run_sums<F>(heads, v);
+    if (ok && run_last(heads)) lds_add_row<F>(&acc[slot * F], v);
 }
 
 // A bucket's records are stored in point order, so runs of records for one
@@ -105,16 +111,22 @@ __device__ __forceinline__ void add_record_wave(float* acc, bool ok, const BinRe
 constexpr int kAccPre = 8;  // float4 chunks of the slice a thread preloads
 
 template <int D, int F, bool ADAM>
-__global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint32_t T, float* __restrict__ d_tables,
+__global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, LevelArgs lv, float* __restrict__ d_tables,
                                                               AdamArgs adam) {
-    extern __shared__ float acc[];
+    extern __shared__ __attribute__((aligned(16))) float acc[];
     const int S = 1 << plan.s_log2;
     const int b = blockIdx.x;
-    const int l = plan.l0 + b / plan.bpl;
-    const size_t off = ((size_t)l * T + (size_t)(b % plan.bpl) * S) * F;
-    const int n4 = S * F / 4;
+    int l = plan.l0;  // the level whose buckets hold b (uniform over the workgroup)
+    while (l + 1 < plan.l1 && b >= plan.boff[l + 1]) ++l;
+    const int slice = b - plan.boff[l];
+    // slots of this bucket: a whole 2^s slice, or the rest of a level whose
+    // rows are not a multiple of it (a densely stored level)
+    const int64_t left = (int64_t)lv.rows[l] - (int64_t)slice * S;
+    const int cnt = left < S ? (int)left : S;
+    const size_t off = ((size_t)lv.off[l] + (size_t)slice * S) * F;
+    const int n4 = cnt * F / 4;
     const float* base_ptr = ADAM ? adam.param : d_tables;
-    const bool vec = n4 * 4 == S * F && ((uintptr_t)(base_ptr + off) & 15) == 0 && n4 <= kAccPre * kAccBlock;
+    const bool vec = n4 * 4 == cnt * F && ((uintptr_t)(base_ptr + off) & 15) == 0 && n4 <= kAccPre * kAccBlock;
     // The slice's state does not depend on the records: issue its loads first
     // so they overlap the record phase.
     f32x4 P[kAccPre], M[kAccPre], Vv[kAccPre];
@@ -135,18 +147,23 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
     for (int i = threadIdx.x; i < S * F; i += kAccBlock) acc[i] = 0.0f;
     __syncthreads();
     // privatised level: pick up the dense sums whose slot falls in this bucket
+    // (a densely stored level numbers its rows over the same box)
     if (l < plan.P) {
         const int ext = plan.ext[l];
-        const uint32_t want = (uint32_t)(b % plan.bpl), smask = (uint32_t)S - 1u;
+        const SlotRule rule = lv.rule(l);
+        const uint32_t want = (uint32_t)slice, smask = (uint32_t)S - 1u;
         for (int e = plan.doff[l] + threadIdx.x; e < plan.doff[l + 1]; e += kAccBlock) {
             int32_t rem = e - plan.doff[l];
-            uint32_t h = 0;
+            uint32_t h = (uint32_t)rem;
+            if (rule.dext == 0) {
+                h = 0;
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                h ^= (uint32_t)(rem % ext) * hash_prime(i);
-                rem /= ext;
+                for (int i = 0; i < D; ++i) {
+                    h ^= (uint32_t)(rem % ext) * hash_prime(i);
+                    rem /= ext;
+                }
+                h &= rule.mask;
             }
-            h &= T - 1u;
             if ((h >> plan.s_log2) != want) continue;
 #pragma unroll
             for (int j = 0; j < F; ++j) {
@@ -190,7 +207,7 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
             }
         }
     } else {
-        for (int i = threadIdx.x; i < S * F; i += kAccBlock) {
+        for (int i = threadIdx.x; i < cnt * F; i += kAccBlock) {
             const float g = acc[i];
             if constexpr (!ADAM) {
                 d_tables[off + i] += g;
@@ -208,18 +225,20 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, uint
     }
 }
 
-// Launch of the accumulation for one level group (recs = record bytes the
-// group's scatter wrote, for the trace).
+// Launch of the accumulation for one level group.  Its algorithmic bytes
+// (for the trace) are the method's scatter payload (4 bytes per point,
+// level, vertex and feature) plus the update of every table entry.
 template <int D, int F>
-hipError_t launch_accum(const EncodeCall& c, const BinPlan& p, double recs) {
-    const double slots = (double)p.B * (1 << p.s_log2) * F;
+hipError_t launch_accum(const EncodeCall& c, const BinPlan& p, double payload) {
+    double slots = 0.0;  // table entries of the group's levels
+    for (int l = p.l0; l < p.l1; ++l) slots += (double)c.lv.rows[l] * F;
     const size_t lds = (size_t)(F << p.s_log2) * sizeof(float);
     if (c.adam.param) {
-        trace_begin(c.stream, "bin_accum_adam", recs + slots * (c.adam.param_f16 ? 26.0 : 24.0));
-        bin_accum_kernel<D, F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, nullptr, c.adam);
+        trace_begin(c.stream, "bin_accum_adam", payload + slots * (c.adam.param_f16 ? 26.0 : 24.0));
+        bin_accum_kernel<D, F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv, nullptr, c.adam);
     } else {
-        trace_begin(c.stream, "bin_accum", recs + slots * 8.0);
-        bin_accum_kernel<D, F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv.mask + 1u, c.d_tables, c.adam);
+        trace_begin(c.stream, "bin_accum", payload + slots * 8.0);
+        bin_accum_kernel<D, F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv, c.d_tables, c.adam);
     }
     trace_end(c.stream);
     return hipGetLastError();

@@ -114,8 +114,8 @@ __global__ __launch_bounds__(kBinBlock) void bin_count_kernel(int64_t N, const f
         float y[D];
         load_point<Tag, D>(pts, pt, lv.Fn, y);
         for (int l = plan.l0; l < plan.l1; ++l) {
-            const uint32_t bl = (uint32_t)(l - plan.l0) * plan.bpl;
-            visit_level_ex(Tag{}, y, lv.sigma[l], lv.mask,
+            const uint32_t bl = (uint32_t)plan.boff[l];
+            visit_level_ex(Tag{}, y, lv.sigma[l], lv.rule(l),
                            [&](const auto& h, const auto& w, int, const auto& cell, const auto&) {
                 constexpr int K = sizeof(w) / sizeof(float);
                 int32_t e0, stride[D];
@@ -204,8 +204,8 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(int64_t N, const
         for (int l = plan.l0; l < plan.l1; ++l) {
             float g[F];
             RowIO<GT, F>::load(grow + l * F, g);
-            const uint32_t bl = (uint32_t)(l - plan.l0) * plan.bpl;
-            visit_level_ex(Tag{}, y, lv.sigma[l], lv.mask,
+            const uint32_t bl = (uint32_t)plan.boff[l];
+            visit_level_ex(Tag{}, y, lv.sigma[l], lv.rule(l),
                            [&](const auto& h, const auto& w, int, const auto& cell, const auto&) {
                 constexpr int K = sizeof(w) / sizeof(float);
                 int32_t e0, stride[D];
@@ -247,7 +247,8 @@ template <int V>
 constexpr int stage_ppt() { return V > kStageSlots ? 0 : kStageSlots / V; }
 
 // LDS layout of the staged scatter (in 32-bit words): cursors [B], local
-// counts/offsets [bpl + 1], staged keys [CAP], staged values [CAP * F].
+// counts/offsets [bmax + 1] (bmax: the most buckets of one level), staged
+// keys [CAP], staged values [CAP * F].
 struct StageLds {
     size_t cursor, loff, key, val, words;
 };
@@ -264,22 +265,95 @@ __host__ __device__ inline StageLds stage_lds(int B, int bpl) {
     return s;
 }
 
+// Staged record key: the slot within its bucket in the low 16 bits, the
+// bucket within the level above (buckets hold 2^s <= 2^15 slots, and a level
+// has at most 16384 buckets).
+__device__ __forceinline__ uint32_t stage_key(uint32_t h, int s_log2, uint32_t smask) {
+    return (h & smask) | ((h >> s_log2) << 16);
+}
+
+// Sums each run of equal keys across consecutive lanes into the run's last
+// lane and drops the others' records (key = kNoKey).  Every lane of the
+// wave must call it; a wave without runs (random points) returns after one
+// ballot.
+template <int F>
+__device__ __forceinline__ void merge_run_wave(uint32_t& key, float (&v)[F]) {
+    const uint64_t heads = __ballot(!joins_prev(key));
+    if (heads == ~0ull) return;
+    run_sums<F>(heads, v);
+    if (!run_last(heads)) key = kNoKey;
+}
+
+// Count pass for the staged scatter: the same rounds, lanes and merged runs,
+// so each workgroup reserves exactly the records it will write per bucket.
+template <class Tag, int D>
+__global__ __launch_bounds__(kStageBlock) void bin_count_staged_kernel(int64_t N, const float* __restrict__ pts,
+                                                                      LevelArgs lv, BinPlan plan) {
+    constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+    constexpr int PPT = stage_ppt<V>();
+    extern __shared__ uint32_t hist[];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < plan.B; b += kStageBlock) hist[b] = 0;
+    __syncthreads();
+    const uint32_t smask = (1u << plan.s_log2) - 1u;
+    int64_t lo, hi;
+    bin_chunk(N, plan.chunk, lo, hi);
+    for (int64_t r0 = lo; r0 < hi; r0 += (int64_t)kStageBlock * PPT) {
+        float y[PPT][D];
+        bool ok[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int64_t pt = r0 + tid + (int64_t)j * kStageBlock;
+            ok[j] = pt < hi;
+            load_point<Tag, D>(pts, ok[j] ? pt : lo, lv.Fn, y[j]);
+        }
+        for (int l = plan.l0; l < plan.l1; ++l) {
+            const uint32_t bl = (uint32_t)plan.boff[l];
+            uint32_t key[PPT][V];
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) key[j][k] = kNoKey;
+                if (!ok[j]) continue;
+                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.rule(l),
+                               [&](const auto& h, const auto& w, int base, const auto& cell, const auto&) {
+                    constexpr int K = sizeof(w) / sizeof(float);
+                    int32_t e0, stride[D];
+                    if (l < plan.P && dense_cell<D>(plan, l, cell, e0, stride)) return;  // summed in LDS instead
+#pragma unroll
+                    for (int k = 0; k < K; ++k) key[j][base + k] = stage_key(h[k], plan.s_log2, smask);
+                });
+            }
+#pragma unroll
+            for (int j = 0; j < PPT; ++j)
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    // every lane takes part in the shuffle, whether it holds a record or not
+                    const bool joins = joins_prev(key[j][k]);
+                    if (key[j][k] != kNoKey && !joins) atomicAdd(&hist[bl + (key[j][k] >> 16)], 1u);
+                }
+        }
+    }
+    __syncthreads();
+    uint32_t* row = plan.counts + (size_t)blockIdx.x * plan.B;
+    for (int b = tid; b < plan.B; b += kStageBlock) row[b] = hist[b];
+}
+
 template <class Tag, int D, int F, typename GT>
 __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t N, const float* __restrict__ pts,
                                                                        const GT* __restrict__ d_out, LevelArgs lv,
                                                                        BinPlan plan) {
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
     constexpr int PPT = stage_ppt<V>();
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    constexpr uint32_t kNone = kNoKey;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t wave_sum[kStageBlock / 64];
-    const StageLds lay = stage_lds<V, F>(plan.B, plan.bpl);
+    const StageLds lay = stage_lds<V, F>(plan.B, plan.bmax);
     uint32_t* cursor = lds + lay.cursor;
     uint32_t* loff = lds + lay.loff;
     uint32_t* skey = lds + lay.key;
     float* sval = reinterpret_cast<float*>(lds + lay.val);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int bpl = plan.bpl;
 
     const uint32_t* row = plan.counts + (size_t)blockIdx.x * plan.B;
     for (int b = tid; b < plan.B; b += kStageBlock) cursor[b] = plan.base[b] + row[b];
@@ -313,7 +387,8 @@ __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t
                         if (l + q < plan.l1) RowIO<GT, F>::load(grow + (l + q) * F, gch[j][q]);
                 }
             }
-            const uint32_t bl = (uint32_t)(l - plan.l0) * bpl;
+            const uint32_t bl = (uint32_t)plan.boff[l];
+            const int bpl = plan.boff[l + 1] - plan.boff[l];  // buckets of this level
             __syncthreads();  // the previous level's offsets are no longer read
             for (int b = tid; b <= bpl; b += kStageBlock) loff[b] = 0;
             __syncthreads();
@@ -332,21 +407,31 @@ __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t
                     if (li == q)
 #pragma unroll
                         for (int f = 0; f < F; ++f) g[f] = gch[j][q][f];
-                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.mask,
+                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.rule(l),
                                [&](const auto& h, const auto& w, int base, const auto& cell, const auto&) {
                     constexpr int K = sizeof(w) / sizeof(float);
                     int32_t e0, stride[D];
                     if (l < plan.P && dense_cell<D>(plan, l, cell, e0, stride)) return;  // summed in LDS instead
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
-                        const uint32_t b = h[k] >> plan.s_log2;
-                        key[j][base + k] = (h[k] & smask) | (b << 16);
-                        rank[j][base + k] = atomicAdd(&loff[b], 1u);
+                        key[j][base + k] = stage_key(h[k], plan.s_log2, smask);
 #pragma unroll
                         for (int f = 0; f < F; ++f) val[j][base + k][f] = w[k] * g[f];
                     }
                 });
             }
+            // Consecutive lanes hold consecutive points: where they put the
+            // same vertex at the same list position (samples along a ray in
+            // one cell), the run is summed across lanes and leaves as one
+            // record (the count kernel counted runs the same way); then each
+            // kept record takes its rank within its bucket.
+#pragma unroll
+            for (int j = 0; j < PPT; ++j)
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    merge_run_wave<F>(key[j][k], val[j][k]);
+                    if (key[j][k] != kNone) rank[j][k] = atomicAdd(&loff[key[j][k] >> 16], 1u);
+                }
             __syncthreads();
             // exclusive scan of the per-bucket counts; loff[bpl] = round total
             {
@@ -407,7 +492,7 @@ template <class Tag, int D, int F, typename GT>
 __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const float* __restrict__ pts,
                                                                const GT* __restrict__ d_out, LevelArgs lv,
                                                                BinPlan plan) {
-    extern __shared__ float dacc[];
+    extern __shared__ __attribute__((aligned(16))) float dacc[];
     const int n = plan.Dtot * F;
     for (int i = threadIdx.x; i < n; i += kBinBlock) dacc[i] = 0.0f;
     __syncthreads();
@@ -422,7 +507,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const 
         for (int l = 0; l < plan.P; ++l) {
             float g[F];
             RowIO<GT, F>::load(grow + l * F, g);
-            visit_level_ex(Tag{}, y, lv.sigma[l], lv.mask,
+            visit_level_ex(Tag{}, y, lv.sigma[l], lv.rule(l),
                            [&](const auto& h, const auto& w, int, const auto& cell, const auto& offs) {
                 constexpr int K = sizeof(w) / sizeof(float);
                 int32_t e0, stride[D];
@@ -435,7 +520,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const 
                 // coherent points, not the odd pair of random ones.
                 const uint32_t ck = ok ? (uint32_t)e0 : 0xFFFFFFFFu;
                 const bool coherent =
-                    __popcll(__ballot(ok && (threadIdx.x & 63) > 0 && __shfl_up(ck, 1, 64) == ck)) >= 8;
+                    __popcll(__ballot(ok && joins_prev(ck))) >= 8;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     float v[F];
@@ -445,8 +530,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const 
                     if (coherent) {
                         lds_add_wave<F>(dacc, ok, e, v);
                     } else if (ok) {
-#pragma unroll
-                        for (int j = 0; j < F; ++j) lds_add(&dacc[e * F + j], v[j]);
+                        lds_add_row<F>(&dacc[e * F], v);
                     }
                 }
             });
@@ -483,9 +567,25 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
     const double N = (double)c.N, gs = sizeof(GT), rec = sizeof(BinRec<F>);
     const double counts = (double)p.W * p.B * 4.0;
-    const double recs = N * (p.l1 - p.l0 - p.P) * V * rec;  // in-box points emit no records at privatised levels
+    (void)rec;
+    // the method's scatter payload: one binary32 value per point, level,
+    // vertex and feature (however many records carry it)
+    const double payload = N * (p.l1 - p.l0) * V * F * 4.0;
+    // The staged scatter (when its LDS fits) merges runs of one slot across
+    // lanes, and its count pass counts the merged records the same way.
+    bool staged = false;
+    size_t staged_lds = 0;
+    if constexpr (stage_ppt<V>() >= 1) {
+        staged_lds = stage_lds<V, F>(p.B, p.bmax).words * sizeof(uint32_t);
+        staged = staged_lds <= kStageLdsMax;
+    }
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
-    bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
+    if (staged) {
+        if constexpr (stage_ppt<V>() >= 1)
+            bin_count_staged_kernel<Tag, D><<<p.W, kStageBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
+    } else {
+        bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
+    }
     trace_end(c.stream);
     trace_begin(c.stream, "bin_colscan", 2.0 * counts + 4.0 * p.B);
     bin_colscan_kernel<<<(p.B + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, c.stream>>>(p, totals);
@@ -520,17 +620,12 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
             if (e != hipSuccess) return e;
         }
     }
-    trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + recs);
-    bool staged = false;
-    if constexpr (stage_ppt<V>() >= 1) {
-        const size_t staged_lds = stage_lds<V, F>(p.B, p.bpl).words * sizeof(uint32_t);
-        if (staged_lds <= kStageLdsMax) {
+    trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + payload);
+    if (staged) {
+        if constexpr (stage_ppt<V>() >= 1)
             bin_scatter_staged_kernel<Tag, D, F, GT><<<p.W, kStageBlock, staged_lds, c.stream>>>(c.N, c.pts, d_out, c.lv,
                                                                                                p);
-            staged = true;
-        }
-    }
-    if (!staged)
+    } else
         bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv,
                                                                                                 p);
     trace_end(c.stream);
@@ -538,13 +633,12 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
         const hipError_t e = hipStreamWaitEvent(c.stream, aux->join, 0);
         if (e != hipSuccess) return e;
     }
-    return launch_accum<D, F>(c, p, recs);
+    return launch_accum<D, F>(c, p, payload);
 }
 
 template <class Tag, int D, int F>
 hipError_t binned_adjoint(const EncodeCall& c) {
-    BinLayout lay = bin_layout(c.D, c.F, c.lv.L, 31 - __builtin_clz(c.lv.mask + 1u), c.N, Tag::simplex, c.lv.sigma,
-                               (double)c.lv.reach);
+    BinLayout lay = bin_layout(c.D, c.F, c.N, Tag::simplex, c.lv);
     char* ws = (char*)c.workspace;
     for (int g = 0; g < lay.groups; ++g) {
         BinPlan p = bin_plan(lay, g, ws);

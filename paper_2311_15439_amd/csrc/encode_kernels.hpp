@@ -95,17 +95,17 @@ struct RowIO<f16, F> {
 // step above the corner.
 
 template <int D, class Fn>
-__device__ __forceinline__ void visit_level_ex(SimplexTag, const float (&y)[D], float sigma, uint32_t mask,
+__device__ __forceinline__ void visit_level_ex(SimplexTag, const float (&y)[D], float sigma, SlotRule rule,
                                                Fn&& fn) {
     uint32_t h[D + 1], offs[D + 1];
     float w[D + 1];
     int32_t cell[D];
-    SimplexCell<D>::lookup(y, sigma, mask, h, w, cell, offs);
+    SimplexCell<D>::lookup(y, sigma, rule, h, w, cell, offs);
     fn(h, w, 0, cell, offs);
 }
 
 template <int D, class Fn>
-__device__ __forceinline__ void visit_level_ex(GridTag, const float (&x)[D], float sigma, uint32_t mask,
+__device__ __forceinline__ void visit_level_ex(GridTag, const float (&x)[D], float sigma, SlotRule rule,
                                                Fn&& fn) {
     typename GridCell<D>::Low lo;
     GridCell<D>::lookup_low(x, sigma, lo);
@@ -113,7 +113,7 @@ __device__ __forceinline__ void visit_level_ex(GridTag, const float (&x)[D], flo
     for (int half = 0; half < 2; ++half) {
         uint32_t h[GridCell<D>::VH], offs[GridCell<D>::VH];
         float w[GridCell<D>::VH];
-        GridCell<D>::corners(lo, half, mask, h, w);
+        GridCell<D>::corners(lo, half, rule, h, w);
 #pragma unroll
         for (int c = 0; c < GridCell<D>::VH; ++c) offs[c] = (uint32_t)(c + half * GridCell<D>::VH);
         fn(h, w, half * GridCell<D>::VH, lo.cell, offs);
@@ -121,8 +121,8 @@ __device__ __forceinline__ void visit_level_ex(GridTag, const float (&x)[D], flo
 }
 
 template <class Tag, int D, class Fn>
-__device__ __forceinline__ void visit_level(Tag tag, const float (&y)[D], float sigma, uint32_t mask, Fn&& fn) {
-    visit_level_ex(tag, y, sigma, mask,
+__device__ __forceinline__ void visit_level(Tag tag, const float (&y)[D], float sigma, SlotRule rule, Fn&& fn) {
+    visit_level_ex(tag, y, sigma, rule,
                    [&](const auto& h, const auto& w, int base, const auto&, const auto&) { fn(h, w, base); });
 }
 
@@ -147,7 +147,6 @@ template <class Tag, int D, int F, typename TT, typename OT>
 __global__ __launch_bounds__(kBlock) void encode_fwd_kernel(int64_t N, const float* __restrict__ pts,
                                                             const TT* __restrict__ tables, OT* __restrict__ out,
                                                             LevelArgs lv) {
-    const uint32_t mask = lv.mask;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
         float y[D];
@@ -156,11 +155,11 @@ __global__ __launch_bounds__(kBlock) void encode_fwd_kernel(int64_t N, const flo
         // unrolled so that several levels' gathers are in flight together
 #pragma unroll 4
         for (int l = 0; l < lv.L; ++l) {
-            const TT* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * F);
+            const TT* __restrict__ tab = tables + lv.off[l] * F;
             float acc[F];
 #pragma unroll
             for (int j = 0; j < F; ++j) acc[j] = 0.0f;
-            visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto& w, int) {
+            visit_level(Tag{}, y, lv.sigma[l], lv.rule(l), [&](const auto& h, const auto& w, int) {
                 constexpr int K = sizeof(w) / sizeof(float);
                 float v[K][F];
 #pragma unroll
@@ -209,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void encode_twin_kernel(int64_t N, const fl
         f16* __restrict__ orow = out + pt * (int64_t)(lv.L * 2);
 #pragma unroll 4
         for (int l = 0; l < lv.L; ++l) {
-            const f16* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * 2);
+            const f16* __restrict__ tab = tables + lv.off[l] * 2;
             float acc[2] = {0.0f, 0.0f};
             auto add = [&](const auto& h) {
                 constexpr int K = sizeof(h) / sizeof(uint32_t);
@@ -227,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void encode_twin_kernel(int64_t N, const fl
                 twin_simplex_slots<D>(y, lv.sigma[l], mask, h);
                 add(h);
             } else {
-                visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto&, int) { add(h); });
+                visit_level(Tag{}, y, lv.sigma[l], SlotRule{mask, 0}, [&](const auto& h, const auto&, int) { add(h); });
             }
             RowIO<f16, 2>::store(orow + l * 2, acc);
         }
@@ -246,7 +245,6 @@ __global__ __launch_bounds__(kBlock) void encode_input_grad_kernel(int64_t N, co
                                                                    const TT* __restrict__ tables,
                                                                    const GT* __restrict__ d_out,
                                                                    float* __restrict__ d_pts, LevelArgs lv) {
-    const uint32_t mask = lv.mask;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
         float y[D];
@@ -258,13 +256,14 @@ __global__ __launch_bounds__(kBlock) void encode_input_grad_kernel(int64_t N, co
         // unrolled so that several levels' gathers are in flight together
 #pragma unroll 4
         for (int l = 0; l < lv.L; ++l) {
-            const TT* __restrict__ tab = tables + (size_t)l * ((size_t)(mask + 1u) * F);
+            const TT* __restrict__ tab = tables + lv.off[l] * F;
+            const SlotRule rule = lv.rule(l);
             float d[F], g[D];
             RowIO<GT, F>::load(grow + l * F, d);
 #pragma unroll
             for (int m = 0; m < D; ++m) g[m] = 0.0f;
             if constexpr (Tag::simplex) {
-                visit_level_ex(Tag{}, y, lv.sigma[l], mask,
+                visit_level_ex(Tag{}, y, lv.sigma[l], rule,
                                [&](const auto& h, const auto&, int, const auto&, const auto& offs) {
                     float t[D + 1][F];
 #pragma unroll
@@ -287,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void encode_input_grad_kernel(int64_t N, co
                     const float p = y[i] * lv.sigma[l];
                     f[i] = p - floorf(p);
                 }
-                visit_level_ex(Tag{}, y, lv.sigma[l], mask,
+                visit_level_ex(Tag{}, y, lv.sigma[l], rule,
                                [&](const auto& h, const auto& w, int, const auto&, const auto& offs) {
                     constexpr int K = sizeof(w) / sizeof(float);
 #pragma unroll
@@ -332,7 +331,6 @@ template <class Tag, int D, int F, typename GT>
 __global__ __launch_bounds__(kBlock) void encode_bwd_kernel(int64_t N, const float* __restrict__ pts,
                                                             const GT* __restrict__ d_out,
                                                             float* __restrict__ d_tables, LevelArgs lv) {
-    const uint32_t mask = lv.mask;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
         float y[D];
@@ -341,8 +339,8 @@ __global__ __launch_bounds__(kBlock) void encode_bwd_kernel(int64_t N, const flo
         for (int l = 0; l < lv.L; ++l) {
             float g[F];
             RowIO<GT, F>::load(grow + l * F, g);
-            float* __restrict__ tab = d_tables + (size_t)l * ((size_t)(mask + 1u) * F);
-            visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto& w, int) {
+            float* __restrict__ tab = d_tables + lv.off[l] * F;
+            visit_level(Tag{}, y, lv.sigma[l], lv.rule(l), [&](const auto& h, const auto& w, int) {
                 constexpr int K = sizeof(w) / sizeof(float);
 #pragma unroll
                 for (int k = 0; k < K; ++k)
@@ -359,7 +357,6 @@ template <class Tag, int D>
 __global__ __launch_bounds__(kBlock) void encode_debug_kernel(int64_t N, const float* __restrict__ pts,
                                                               uint32_t* __restrict__ idx,
                                                               float* __restrict__ wout, LevelArgs lv) {
-    const uint32_t mask = lv.mask;
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t pt = (int64_t)blockIdx.x * kBlock + threadIdx.x; pt < N; pt += stride) {
@@ -367,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void encode_debug_kernel(int64_t N, const f
         load_point<Tag, D>(pts, pt, lv.Fn, y);
         for (int l = 0; l < lv.L; ++l) {
             const int64_t base = (pt * lv.L + l) * V;
-            visit_level(Tag{}, y, lv.sigma[l], mask, [&](const auto& h, const auto& w, int b0) {
+            visit_level(Tag{}, y, lv.sigma[l], lv.rule(l), [&](const auto& h, const auto& w, int b0) {
                 constexpr int K = sizeof(w) / sizeof(float);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {

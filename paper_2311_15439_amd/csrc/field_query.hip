@@ -65,7 +65,7 @@ __device__ __forceinline__ h8 encode_quarter(const spx_field& f, const float* __
         const int l = 4 * q + lv;
         const f16* __restrict__ tab = tables + (size_t)l * level_elems;
         float acc[2] = {0.0f, 0.0f};
-        visit_level(Tag{}, y, f.sigma[l], f.mask, [&](const auto& h, const auto& w, int) {
+        visit_level(Tag{}, y, f.sigma[l], SlotRule{f.mask, 0}, [&](const auto& h, const auto& w, int) {
             constexpr int K = sizeof(w) / sizeof(float);
             float v[K][2];
 #pragma unroll

@@ -1,6 +1,9 @@
 // Device-side lookup of one point at one level: which table slots, with
 // which weights.  Shared by the forward, adjoint and debug kernels so that
 // the three see exactly the same simplex, slots and binary32 weights.
+// A level's slot rule (SlotRule) either hashes the vertex into the level's
+// power-of-two table or, for a level stored densely, numbers the vertices
+// of its box (coordinates clamped to the box).
 //
 // Binary32 index path (fixed operation order, no contraction):
 //   skew (Eq. 2):   s = x_0 + x_1 + ... (left to right), t = s * F_n,
@@ -15,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "spx_internal.h"
 
 namespace spx {
 
@@ -51,7 +56,7 @@ struct SimplexCell {
     // h[k], w[k] for k = 0..D: the walk's vertices.  cell receives the cell
     // corner and offs[k] the set of axes (bit i = axis i) on which vertex k
     // is one step above it; callers that ignore them pay nothing (inlined).
-    __device__ __forceinline__ static void lookup(const float (&y)[D], float sigma, uint32_t mask,
+    __device__ __forceinline__ static void lookup(const float (&y)[D], float sigma, SlotRule rule,
                                                   uint32_t (&h)[V], float (&w)[V], int32_t (&cell)[D],
                                                   uint32_t (&offs)[V]) {
 #pragma clang fp contract(off)
@@ -96,8 +101,38 @@ struct SimplexCell {
                 hk ^= (r[i] < k) ? a[i] + hash_prime(i) : a[i];
                 ok |= (r[i] < k) ? (1u << i) : 0u;
             }
-            h[k] = hk & mask;
+            h[k] = hk & rule.mask;
             offs[k] = ok;
+        }
+        select_rows(cell, rule.dext, offs, h);
+    }
+
+    // Rows of a densely stored level (dext > 0): each vertex's coordinates
+    // clamped to the box [0, dext - 1] (points outside the unit cube), axis 0
+    // fastest.  Computed for every level and selected without a branch, so
+    // that the gathers of several levels can stay in flight together; for a
+    // hashed level (dext == 0) the hashed rows are kept.
+    template <int K>
+    __device__ __forceinline__ static void select_rows(const int32_t (&cell)[D], int32_t dext,
+                                                       const uint32_t (&offs)[K], uint32_t (&h)[K]) {
+        const int32_t top = dext - 1;
+        int32_t st[D];
+        int32_t stride = 1;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            st[i] = stride;
+            stride *= dext;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            int32_t idx = 0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                int32_t v = cell[i] + (int32_t)((offs[k] >> i) & 1u);
+                v = v < 0 ? 0 : (v > top ? top : v);
+                idx += v * st[i];
+            }
+            h[k] = dext > 0 ? (uint32_t)idx : h[k];
         }
     }
 };
@@ -155,7 +190,7 @@ struct GridCell {
     }
 
     // Corner c_low + half * 2^(n-1).
-    __device__ __forceinline__ static void corners(const Low& lo, int half, uint32_t mask,
+    __device__ __forceinline__ static void corners(const Low& lo, int half, SlotRule rule,
                                                    uint32_t (&h)[VH], float (&w)[VH]) {
 #pragma clang fp contract(off)
         const float t = half ? lo.ft : lo.gt;
@@ -163,8 +198,12 @@ struct GridCell {
 #pragma unroll
         for (int c = 0; c < VH; ++c) {
             w[c] = lo.w[c] * t;
-            h[c] = (lo.h[c] ^ ht) & mask;
+            h[c] = (lo.h[c] ^ ht) & rule.mask;
         }
+        uint32_t offs[VH];
+#pragma unroll
+        for (int c = 0; c < VH; ++c) offs[c] = (uint32_t)c | ((uint32_t)half << (D - 1));
+        SimplexCell<D>::select_rows(lo.cell, rule.dext, offs, h);
     }
 };
 

@@ -26,13 +26,30 @@ AuxStream* aux_stream(std::unique_lock<std::mutex>& lock);
 struct SimplexTag { static constexpr bool simplex = true; };
 struct GridTag { static constexpr bool simplex = false; };
 
+// How one level maps a lattice vertex to a row of its table: hashed into
+// mask + 1 rows (dext == 0), or stored densely over the box of dext^n
+// vertices, vertex v at row sum_i clamp(v_i, 0, dext - 1) dext^i (dext > 0).
+struct SlotRule {
+    uint32_t mask;
+    int32_t dext;
+};
+
 // Per-call level parameters, passed to the kernels by value.
 struct LevelArgs {
     float sigma[32];  // binary32 multiplier of level l
-    float reach;      // largest pre-scale coordinate of the unit cube (sqrt(n+1) or 1)
     float Fn;         // skew factor F_n in binary32
-    uint32_t mask;    // T - 1
+    uint32_t mask;    // T - 1 (rows of the largest level)
     int32_t L;        // number of levels
+    uint32_t dense;   // bit l: level l is stored densely
+    int32_t ext[32];  // per axis, extent of the vertex box the closed unit cube reaches at level l
+    uint32_t rows[32];  // rows of level l's table (a power of two when hashed)
+    uint64_t off[32];   // first row of level l
+    // Without a branch (a conditional load of ext[l] would split the level
+    // loop and keep the gathers of successive levels from overlapping).
+    __host__ __device__ SlotRule rule(int l) const {
+        const int32_t on = -(int32_t)((dense >> l) & 1u);
+        return SlotRule{rows[l] - 1u, ext[l] & on};
+    }
 };
 
 // Adam hyper-parameters and state for the fused adjoint + optimizer path
@@ -54,7 +71,7 @@ enum class EncodeOp { Forward, Adjoint, AdjointBinned, Debug, Twin, InputGrad };
 struct BinPlan {
     int l0, l1;       // levels [l0, l1) of this group
     int s_log2;       // slots per bucket = 2^s_log2
-    int bpl;          // buckets per level
+    int bmax;         // largest bucket count of one level in the group
     int B;            // buckets in this group
     int W;            // workgroups of the count, coarse and scatter passes
     int64_t chunk;    // points per workgroup
@@ -62,6 +79,7 @@ struct BinPlan {
     int Dtot;         // dense entries over the privatised levels
     int ext[32];      // dense box extent per privatised level
     int doff[33];     // first dense entry of each privatised level
+    int boff[33];     // first bucket of level l in the group (levels l0..l1)
     uint32_t* counts;  // [W][B]
     uint32_t* base;    // [B + 1]
     void* recs;        // records
@@ -69,10 +87,12 @@ struct BinPlan {
     float* gdense;     // [Dtot * F] their total
 };
 
-// Sizes shared by every group; a pure function of the encoding, its level
-// multipliers and N, so the workspace query and the launch agree.
+// Sizes shared by every group; a pure function of the encoding's level
+// parameters and N, so the workspace query and the launch agree.
 struct BinLayout {
-    int L, lpg, groups, s_log2, bpl, Bmax, W, rec_bytes, V, P, Dtot;
+    int L, groups, s_log2, Bmax, W, rec_bytes, V, P, Dtot, lmax;
+    int nb[32];       // buckets of level l: ceil(rows / 2^s)
+    int gl[33];       // group g holds levels [gl[g], gl[g + 1])
     int ext[32];
     int doff[33];
     int64_t N, chunk;
@@ -82,12 +102,9 @@ struct BinLayout {
 
 inline size_t bin_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// sigma: binary32 level multipliers; reach: largest skewed coordinate of a
-// point of the unit cube before scaling (sqrt(n+1) for the simplex, 1 for
-// the grid).
-inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simplex, const float* sigma,
-                            double reach) {
+inline BinLayout bin_layout(int D, int F, int64_t N, bool simplex, const LevelArgs& lv) {
     BinLayout b{};
+    const int L = lv.L;
     b.L = L;
     b.N = N;
     b.V = simplex ? D + 1 : (1 << D);
@@ -98,41 +115,60 @@ inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simp
     // share a CU, but the scatter's per-bucket runs of records would be half
     // as long, and its record stores are bound by those runs.  At most 16384
     // buckets per level for T <= 2^26.
+    int log2T = 31 - __builtin_clz(lv.mask + 1u);
     int s = 15 - lf;
     if (s > log2T) s = log2T;
     b.s_log2 = s;
-    b.bpl = 1 << (log2T - s);
-    b.ok = b.bpl <= 16384 && N >= 0;
-    // levels per group: at most 16384 buckets, fewer than 2^31 records, and
-    // at most 2 GiB of records (the count, scan, scatter and accumulation
-    // passes repeat per group, so fewer groups are faster; 2 GiB of 288 GB)
-    int lpg = 16384 / b.bpl;
-    if (lpg > L) lpg = L;
+    b.ok = N >= 0;
+    for (int l = 0; l < L; ++l) {
+        b.nb[l] = (int)(((uint64_t)lv.rows[l] + (1u << s) - 1) >> s);
+        if (b.nb[l] > 16384) b.ok = false;
+    }
+    // level groups: consecutive levels while the group holds at most 16384
+    // buckets, fewer than 2^31 records and at most 2 GiB of records (the
+    // count, scan, scatter and accumulation passes repeat per group, so fewer
+    // groups are faster; 2 GiB of 288 GB)
     const double per_level = (double)N * b.V;
-    while (lpg > 1 && (per_level * lpg >= 2147483647.0 || per_level * lpg * b.rec_bytes > 2147483648.0)) --lpg;
-    if (per_level * lpg >= 2147483647.0) b.ok = false;
-    if (lpg < 1) { lpg = 1; b.ok = false; }
-    b.lpg = lpg;
-    b.groups = (L + lpg - 1) / lpg;
-    b.Bmax = lpg * b.bpl;
+    if (per_level >= 2147483647.0) b.ok = false;
+    b.groups = 0;
+    b.Bmax = 0;
+    b.lmax = 0;
+    int l = 0;
+    while (l < L && b.groups < 32) {
+        const int g0 = l;
+        int nbk = 0;
+        while (l < L) {
+            const int k = l - g0 + 1;
+            const bool fits = nbk + b.nb[l] <= 16384 && per_level * k < 2147483647.0 &&
+                              per_level * k * b.rec_bytes <= 2147483648.0;
+            if (!fits && l > g0) break;
+            nbk += b.nb[l];
+            ++l;
+        }
+        b.gl[b.groups++] = g0;
+        if (nbk > b.Bmax) b.Bmax = nbk;
+        if (l - g0 > b.lmax) b.lmax = l - g0;
+    }
+    b.gl[b.groups] = L;
+    if (l < L) b.ok = false;
     int64_t W = (N + 255) / 256;
     b.W = (int)(W < 512 ? (W > 0 ? W : 1) : 512);
     b.chunk = (N + b.W - 1) / b.W;
-    // privatised coarse levels: the prefix of group 0 whose dense boxes fit
+    // privatised coarse levels: the prefix of group 0 whose vertex boxes fit
     // in 96 KiB of binary32 accumulators
     const int dense_max = (96 * 1024) / (4 * F);
     b.P = 0;
     b.Dtot = 0;
     b.doff[0] = 0;
-    for (int l = 0; l < lpg && l < 32; ++l) {
-        const double e = floor((double)sigma[l] * reach) + 2.0;
+    for (int q = 0; q < b.gl[1] && q < 32; ++q) {
+        const double e = (double)lv.ext[q];
         double size = 1.0;
         for (int i = 0; i < D; ++i) size *= e;
         if (size > (double)(dense_max - b.Dtot)) break;
-        b.ext[l] = (int)e;
+        b.ext[q] = (int)e;
         b.Dtot += (int)size;
-        b.P = l + 1;
-        b.doff[l + 1] = b.Dtot;
+        b.P = q + 1;
+        b.doff[q + 1] = b.Dtot;
     }
     size_t off = 0;
     b.off_counts = off;
@@ -146,24 +182,32 @@ inline BinLayout bin_layout(int D, int F, int L, int log2T, int64_t N, bool simp
     b.off_gdense = off;
     off = bin_align(off + (size_t)b.Dtot * F * 4);
     b.off_recs = off;
-    off = bin_align(off + (size_t)N * lpg * b.V * b.rec_bytes);
+    off = bin_align(off + (size_t)N * b.lmax * b.V * b.rec_bytes);
     b.total_bytes = off;
     return b;
 }
 
 inline BinPlan bin_plan(const BinLayout& lay, int g, char* ws) {
     BinPlan p;
-    p.l0 = g * lay.lpg;
-    p.l1 = p.l0 + lay.lpg < lay.L ? p.l0 + lay.lpg : lay.L;
+    p.l0 = lay.gl[g];
+    p.l1 = lay.gl[g + 1];
     p.s_log2 = lay.s_log2;
-    p.bpl = lay.bpl;
-    p.B = (p.l1 - p.l0) * lay.bpl;
     p.W = lay.W;
     p.chunk = lay.chunk;
     p.P = g == 0 ? lay.P : 0;
     p.Dtot = g == 0 ? lay.Dtot : 0;
     for (int l = 0; l < 32; ++l) p.ext[l] = lay.ext[l];
     for (int l = 0; l < 33; ++l) p.doff[l] = lay.doff[l];
+    for (int l = 0; l < 33; ++l) p.boff[l] = 0;
+    int acc = 0;
+    p.bmax = 0;
+    for (int l = p.l0; l < p.l1; ++l) {
+        p.boff[l] = acc;
+        acc += lay.nb[l];
+        if (lay.nb[l] > p.bmax) p.bmax = lay.nb[l];
+    }
+    p.boff[p.l1] = acc;
+    p.B = acc;
     p.counts = (uint32_t*)(ws + lay.off_counts);
     p.base = (uint32_t*)(ws + lay.off_base);
     p.recs = ws + lay.off_recs;

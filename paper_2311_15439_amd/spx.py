@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "spx.h")
 SPX_OK, SPX_EINVAL, SPX_EALIGN, SPX_EUNSUPPORTED, SPX_EHIP = 0, 1, 2, 3, 4
 SPX_F32, SPX_F16 = 0, 1
 SPX_SIMPLEX, SPX_GRID = 0, 1
+SPX_LAYOUT_HASHED, SPX_LAYOUT_SIZED = 0, 1
 MAX_DIMS, MAX_LEVELS = 6, 32
 
 
@@ -33,7 +34,7 @@ class SpxError(RuntimeError):
 class spx_encoding(C.Structure):
     _fields_ = [("n_dims", C.c_int32), ("n_levels", C.c_int32), ("log2_T", C.c_int32),
                 ("n_feat", C.c_int32), ("table_dtype", C.c_int32), ("cell", C.c_int32),
-                ("equal_memory", C.c_int32), ("res", C.c_int32 * MAX_LEVELS)]
+                ("equal_memory", C.c_int32), ("res", C.c_int32 * MAX_LEVELS), ("layout", C.c_int32)]
 
 
 class spx_field(C.Structure):
@@ -65,6 +66,7 @@ _SIGNATURES = {
     "spx_level_resolutions": (C.c_int, [C.c_double, C.c_double, C.c_int32, _P]),
     "spx_level_scales": (C.c_int, [_P, _P]),
     "spx_hash_primes": (C.c_int, [_P]),
+    "spx_table_layout": (C.c_int, [_P, _P, _P, _P, _P]),
     "spx_encode_fwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, C.c_int32, _P]),
     "spx_encode_bwd": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P, C.c_size_t, _P]),
     "spx_encode_bwd_workspace": (C.c_int, [_P, C.c_int64, _P]),
@@ -132,16 +134,22 @@ class Encoding:
     table_dtype: int = SPX_F16
     cell: int = SPX_SIMPLEX
     equal_memory: bool = False
+    layout: int = SPX_LAYOUT_HASHED
     _c: spx_encoding = field(default=None, init=False, repr=False)
+    _shape: tuple = field(default=None, init=False, repr=False)
 
     def __post_init__(self):
         e = spx_encoding()
         e.n_dims, e.n_levels, e.log2_T = self.n_dims, len(self.res), self.log2_T
         e.n_feat, e.table_dtype, e.cell = self.n_feat, self.table_dtype, self.cell
         e.equal_memory = int(self.equal_memory)
+        e.layout = int(self.layout)
         for i, r in enumerate(list(self.res)[:MAX_LEVELS]):
             e.res[i] = int(r)
         self._c = e
+        self._shape = (self.n_levels, 1 << self.log2_T, self.n_feat)
+        if self.layout != SPX_LAYOUT_HASHED:
+            self._shape = (spx_table_layout(self)["total_rows"], self.n_feat)
 
     @property
     def n_levels(self) -> int:
@@ -153,7 +161,8 @@ class Encoding:
 
     @property
     def table_shape(self):
-        return (self.n_levels, 1 << self.log2_T, self.n_feat)
+        """[L, T, F] for the hashed layout; [rows of all levels, F] otherwise."""
+        return self._shape
 
     def ref(self):
         return C.byref(self._c)
@@ -217,6 +226,20 @@ def spx_level_scales(enc: Encoding):
     out = (C.c_float * enc.n_levels)()
     _check(lib().spx_level_scales(enc.ref(), C.cast(out, C.c_void_p)), "spx_level_scales")
     return [float(v) for v in out]
+
+
+def spx_table_layout(enc: Encoding):
+    """Per level: rows, box extent, dense flag; total rows and row offsets."""
+    L = enc.n_levels
+    rows, ext, dense, total = (C.c_int64 * L)(), (C.c_int32 * L)(), (C.c_int32 * L)(), C.c_int64(0)
+    _check(lib().spx_table_layout(enc.ref(), C.cast(rows, C.c_void_p), C.cast(ext, C.c_void_p),
+                                  C.cast(dense, C.c_void_p), C.byref(total)), "spx_table_layout")
+    r = [int(v) for v in rows]
+    offs = [0]
+    for v in r:
+        offs.append(offs[-1] + v)
+    return {"rows": r, "box_extent": [int(v) for v in ext], "dense": [bool(v) for v in dense],
+            "total_rows": int(total.value), "offsets": offs}
 
 
 def spx_hash_primes():

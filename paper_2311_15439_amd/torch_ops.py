@@ -97,7 +97,8 @@ class FieldFn(torch.autograd.Function):
         N = pts.shape[0]
         feats = torch.empty((N, enc.n_levels * enc.n_feat), dtype=torch.float16, device=pts.device)
         y = torch.empty((N, mlp.d_out), dtype=torch.float32, device=pts.device)
-        if enc.n_dims in (2, 3) and enc.n_levels == 16 and enc.n_feat == 2 and mlp.d_in == 32:
+        if (enc.n_dims in (2, 3) and enc.n_levels == 16 and enc.n_feat == 2 and mlp.d_in == 32
+                and enc.layout == spx.SPX_LAYOUT_HASHED):
             # one kernel: features go from the gathers to the matrix cores in registers
             spx.spx_encode_mlp_fwd(enc, mlp, pts, table_f16, *W16, y, feats=feats)
         else:
@@ -130,18 +131,19 @@ class FieldFn(torch.autograd.Function):
 
 class SimplexEncoding(torch.nn.Module):
     """Multiresolution simplex (or grid) hash encoding with binary32 master
-    tables ``params`` [L, T, F] and a binary16 copy used by the forward."""
+    tables ``params`` (shape ``enc.table_shape``: [L, T, F] for the hashed
+    layout) and a binary16 copy used by the forward."""
 
     def __init__(self, n_dims: int, n_levels: int = 16, log2_T: int = 19, n_feat: int = 2,
                  n_min: float = 16, n_max: Optional[float] = None, growth: Optional[float] = None,
                  cell: int = spx.SPX_SIMPLEX, equal_memory: bool = False, init_scale: float = 1e-4,
-                 seed: int = 0, device="cuda"):
+                 seed: int = 0, device="cuda", layout: int = spx.SPX_LAYOUT_HASHED):
         super().__init__()
         if growth is None:
             growth = 1.5 if n_max is None else (n_max / n_min) ** (1.0 / max(n_levels - 1, 1))
         res = spx.spx_level_resolutions(n_min, growth, n_levels)
         self.enc = spx.Encoding(n_dims, res, log2_T, n_feat, table_dtype=spx.SPX_F16, cell=cell,
-                                equal_memory=equal_memory)
+                                equal_memory=equal_memory, layout=layout)
         init = np.random.default_rng(seed).uniform(-init_scale, init_scale, self.enc.table_shape)
         self.params = torch.nn.Parameter(torch.from_numpy(init.astype(np.float32)).to(device))
         self.register_buffer("table_f16", torch.empty(self.enc.table_shape, dtype=torch.float16, device=device))

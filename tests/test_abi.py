@@ -25,7 +25,7 @@ def test_exports_every_header_symbol():
 
 
 def test_abi_version_and_status_strings():
-    assert spx.spx_abi_version() == 1
+    assert spx.spx_abi_version() == 2
     for s in range(5):
         assert spx.spx_status_str(s).startswith("SPX_")
 
@@ -50,6 +50,42 @@ def test_level_scales_match_oracle(n, cell, em):
     ours = np.array(spx.spx_level_scales(enc), np.float32)
     theirs = oracle.level_scales(n, res, cell=cell, equal_memory=em and cell == spx.SPX_SIMPLEX)
     np.testing.assert_array_equal(ours, theirs)
+
+
+@pytest.mark.parametrize("n,res,log2_T,cell", [
+    (2, [16, 24, 36, 54], 14, spx.SPX_SIMPLEX), (3, [4, 9, 20, 45, 90], 16, spx.SPX_SIMPLEX),
+    (2, [5, 12, 130, 700], 14, spx.SPX_GRID), (4, [3, 6, 11, 19], 12, spx.SPX_SIMPLEX),
+    (3, [6, 30, 150], 18, spx.SPX_GRID), (6, [16, 28, 50, 90], 20, spx.SPX_SIMPLEX),
+    (1, [7, 70, 7000], 10, spx.SPX_SIMPLEX)])
+@pytest.mark.parametrize("layout", [spx.SPX_LAYOUT_HASHED, spx.SPX_LAYOUT_SIZED])
+def test_table_layout_matches_oracle(n, res, log2_T, cell, layout):
+    """Rows, box extents and dense flags per level, computed by the library
+    and by the oracle from the same reading of Sec. 5.2, agree exactly."""
+    g = spx.spx_table_layout(spx.Encoding(n, res, log2_T, cell=cell, layout=layout))
+    o = oracle.table_layout(oracle.Encoding(n, res, log2_T, cell=cell, layout=layout))
+    assert g["rows"] == list(o["rows"]) and g["box_extent"] == list(o["extent"]) and g["dense"] == list(o["dense"])
+    assert g["offsets"] == list(o["offsets"]) and g["total_rows"] == o["offsets"][-1]
+
+
+@pytest.mark.parametrize("w", [inputs.IMAGE_2D, inputs.VOLUME_3D] + [inputs.sweep_workload(n) for n in range(2, 7)])
+def test_sized_layout_of_the_workloads(w):
+    res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
+    for cell in (spx.SPX_SIMPLEX, spx.SPX_GRID):
+        g = spx.spx_table_layout(spx.Encoding(w.n_dims, res, w.log2_T, cell=cell, layout=spx.SPX_LAYOUT_SIZED))
+        o = oracle.table_layout(oracle.Encoding(w.n_dims, res, w.log2_T, cell=cell, layout=oracle.SIZED))
+        assert g["rows"] == list(o["rows"]) and g["dense"] == list(o["dense"])
+        assert g["total_rows"] <= w.n_levels << w.log2_T
+
+
+def test_layout_argument_checks():
+    L = spx.lib()
+    e = spx.Encoding(2, [16], 14)
+    e._c.layout = 7
+    assert L.spx_table_layout(e.ref(), None, None, None, None) == spx.SPX_EINVAL
+    enc = spx.Encoding(2, [16] * 16, 14, layout=spx.SPX_LAYOUT_SIZED)
+    f = spx.spx_field()
+    fake = C.c_void_p(0x10000)
+    assert L.spx_field_init(enc.ref(), fake, fake, fake, fake, 3, C.byref(f)) == spx.SPX_EUNSUPPORTED
 
 
 def _status(fn, *args):

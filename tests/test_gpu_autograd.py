@@ -120,3 +120,90 @@ def test_encoding_fn_input_gradient():
     ref, mag = oracle.encode_input_grad(oe, pts, m.table_f16.cpu().numpy(), G.astype(np.float64), with_mag=True)
     tol = 2 * (2 + 6 + 4 + 4 + 8) * 2.0 ** -24 * mag + 1e-30
     assert (np.abs(tp.grad.cpu().numpy() - ref) <= tol).all()
+
+
+@pytest.mark.parametrize("layout", [spx.SPX_LAYOUT_HASHED, spx.SPX_LAYOUT_SIZED])
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+def test_table_gradient_central_differences_on_gpu(cell, layout):
+    """Autograd's table gradient (the binned adjoint) against central
+    differences of the GPU forward, entry by entry.  The encoding is linear
+    in the stored (binary16) table values, so the difference quotient over
+    the actual binary16 step is the derivative up to the forward's rounding
+    (loss summed in binary64)."""
+    from paper_2311_15439_amd.torch_ops import SimplexEncoding
+    m = SimplexEncoding(3, n_levels=4, log2_T=12, n_min=6, n_max=90, init_scale=0.5, seed=11, cell=cell,
+                        layout=layout)
+    pts = torch.from_numpy(inputs.uniform_points(4000, 3, 12)).to(DEV)
+    d = torch.from_numpy(inputs.gradients(4000, 8, 13)).to(DEV).double()
+
+    def loss():
+        return float((m(pts).double() * d).sum())
+
+    (m(pts).double() * d).sum().backward()
+    g = m.params.grad.detach().cpu().numpy().reshape(-1)
+    flat = m.params.detach().view(-1)
+    rows = np.flatnonzero(np.abs(g) > 1e-3)
+    sel = np.random.default_rng(14).choice(rows, 16, replace=False)
+    for i in sel:
+        old = float(flat[i])
+        with torch.no_grad():
+            flat[i] = old + 0.25
+        up, a = loss(), float(m.table_f16.view(-1)[i])
+        with torch.no_grad():
+            flat[i] = old - 0.25
+        dn, b = loss(), float(m.table_f16.view(-1)[i])
+        with torch.no_grad():
+            flat[i] = old
+        fd = (up - dn) / (a - b)
+        assert abs(fd - g[i]) <= 1e-4 * abs(g[i]) + 1e-4, (i, fd, g[i])
+
+
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+def test_input_gradient_central_differences_on_gpu(cell):
+    """Autograd's gradient with respect to the points against central
+    differences of the GPU forward (binary32 tables and outputs), at points
+    whose lookups do not change across the step (the encoding is affine
+    inside a simplex or cell).  The forward rounds the skewed coordinate
+    (below 2) and the scaled one to binary32 at each of the two evaluation
+    points, so the scaled step sigma_l * dp of every axis is off by up to
+    3 sigma_l 2^-23 per evaluation; through the simplex's skew every axis
+    moves, and sum_i |d f / d p_i| is at most 3 times the derivative's
+    magnitude over sigma (the oracle's sum over absolute values, with
+    F_3 = 1/3), so the quotient is within 9 * 2^-23 / h of the magnitude
+    (12 used)."""
+    n, res, log2_T = 3, [5, 17, 60], 14
+    enc = spx.Encoding(n, res, log2_T, 2, table_dtype=spx.SPX_F32, cell=cell)
+    tab = torch.from_numpy(inputs.tables(3, 1 << log2_T, 2, 1.0, 15, False)).to(DEV)
+    x = torch.from_numpy(inputs.uniform_points(512, n, 16)).to(DEV)
+    d = torch.from_numpy(inputs.gradients(512, 6, 17)).to(DEV)
+    dx = torch.empty_like(x)
+    spx.spx_encode_input_grad(enc, x, tab, d, dx)
+    h = 2.0 ** -12
+    _, mag = oracle.encode_input_grad(oracle.Encoding(n, res, log2_T, 2, table_dtype=oracle.F32, cell=cell),
+                                      x.cpu().numpy(), tab.cpu().numpy(), d.cpu().numpy().astype(np.float64),
+                                      with_mag=True)
+    out = torch.empty((512, 6), device=DEV)
+    idx = torch.empty((512, 3, enc.n_vertices), dtype=torch.int32, device=DEV)
+    spx.spx_encode_debug(enc, x, idx=idx)
+    ref_idx = idx.clone()
+    checked = 0
+    for i in range(n):
+        e = torch.zeros(n, device=DEV)
+        e[i] = h
+        f = []
+        same = torch.ones(512, dtype=torch.bool, device=DEV)
+        for s in (+1, -1):
+            xs = (x + s * e).contiguous()
+            spx.spx_encode_fwd(enc, xs, tab, out)
+            f.append((out.double() * d.double()).sum(1))
+            spx.spx_encode_debug(enc, xs, idx=idx)
+            same &= (idx == ref_idx).all(2).all(1)
+        step = ((x[:, i] + h) - (x[:, i] - h)).double()
+        fd = (f[0] - f[1]) / step
+        got = dx[:, i].double()
+        ok = same.cpu().numpy()
+        err = (fd - got).abs().cpu().numpy()[ok]
+        tol = (12 * 2.0 ** -23 / h + 1e-5) * mag[ok, i] + 1e-4
+        assert (err <= tol).all(), float((err / tol).max())
+        checked += int(ok.sum())
+    assert checked > 1000

@@ -1,0 +1,186 @@
+"""GPU parity of the per-level table layout (Sec. 5.2, Hash Table Selection)
+through the C ABI: with SPX_LAYOUT_SIZED a level whose vertex box fits in T
+rows is stored densely (no collisions) and a larger one is hashed into the
+smallest power of two that holds the share of the box a simplex level
+uses.  The same bars as the hashed layout (tests/test_gpu_encode.py): slots
+and binary32 weights bit-exact, features within 1e-5 of their magnitude,
+table gradients within the summation bound per row."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_15439_amd import inputs, spx
+from test_gpu_encode import _check_fwd, _gpu_bwd, _gpu_debug, _gpu_fwd, _special_points
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+LAYOUT_CASES = [
+    # n, res, log2_T, F, binary16 tables, cell
+    (2, [16, 24, 36, 54], 14, 2, False, spx.SPX_SIMPLEX),          # every level dense
+    (2, [5, 12, 130, 700, 3000], 14, 2, True, spx.SPX_GRID),      # dense, then hashed at T
+    (3, [4, 9, 20, 45, 90, 200], 16, 2, True, spx.SPX_SIMPLEX),    # dense, sized below T, capped at T
+    (3, [6, 30, 150], 18, 4, False, spx.SPX_GRID),
+    (4, [3, 6, 11, 19], 12, 1, False, spx.SPX_SIMPLEX),
+    (6, [3, 5, 8, 16], 14, 2, True, spx.SPX_SIMPLEX),
+    (1, [7, 70, 7000], 10, 8, False, spx.SPX_SIMPLEX),
+]
+
+
+def _ids(c):
+    return f"n{c[0]}L{len(c[1])}F{c[3]}{'h' if c[4] else 'f'}c{c[5]}"
+
+
+def _pair(n, res, log2_T, F, f16, cell):
+    g = spx.Encoding(n, list(res), log2_T, n_feat=F, table_dtype=spx.SPX_F16 if f16 else spx.SPX_F32, cell=cell,
+                     layout=spx.SPX_LAYOUT_SIZED)
+    o = oracle.Encoding(n, list(res), log2_T, n_feat=F, table_dtype=oracle.F16 if f16 else oracle.F32, cell=cell,
+                        layout=oracle.SIZED)
+    return g, o
+
+
+def _tables(enc, f16, seed):
+    t = inputs.dense_values(enc.table_shape, seed)
+    return t.astype(np.float16) if f16 else t.astype(np.float32)
+
+
+def _points(n, N, seed):
+    """Uniform points, the cube's corners and faces, ties, and points outside
+    the cube (whose coordinates are clamped to the box on the dense levels)."""
+    return np.concatenate([inputs.uniform_points(N, n, seed), _special_points(n, np.random.default_rng(seed)),
+                           -1.5 + 4.0 * inputs.uniform_points(97, n, seed + 1)])
+
+
+def test_layout_has_dense_and_hashed_levels():
+    kinds = set()
+    for n, res, log2_T, F, f16, cell in LAYOUT_CASES:
+        lay = spx.spx_table_layout(_pair(n, res, log2_T, F, f16, cell)[0])
+        kinds |= {("dense" if d else ("sized" if r < 1 << log2_T else "T")) for d, r in zip(lay["dense"], lay["rows"])}
+    assert kinds == {"dense", "sized", "T"}
+
+
+@pytest.mark.parametrize("case", LAYOUT_CASES, ids=_ids)
+def test_layout_debug_bit_exact(case):
+    n, res, log2_T, F, f16, cell = case
+    g, o = _pair(n, res, log2_T, F, f16, cell)
+    pts = _points(n, 3000, 10 + n)
+    idx, w = _gpu_debug(g, pts)
+    ref = oracle.encode_debug(o, pts)
+    np.testing.assert_array_equal(idx, ref["idx"])
+    np.testing.assert_array_equal(w.view(np.uint32), ref["w32"].view(np.uint32))
+
+
+@pytest.mark.parametrize("out_f16", [False, True])
+@pytest.mark.parametrize("case", LAYOUT_CASES, ids=_ids)
+def test_layout_fwd_parity(case, out_f16):
+    n, res, log2_T, F, f16, cell = case
+    g, o = _pair(n, res, log2_T, F, f16, cell)
+    pts = _points(n, 4000, 20 + n)
+    tab = _tables(g, f16, 30 + n)
+    _check_fwd(_gpu_fwd(g, pts, tab, out_f16), oracle.encode_fwd(o, pts, tab), oracle.encode_fwd_absmag(o, pts, tab),
+               out_f16)
+
+
+@pytest.mark.parametrize("binned", [False, True], ids=["atomic", "binned"])
+@pytest.mark.parametrize("case", LAYOUT_CASES, ids=_ids)
+def test_layout_bwd_parity(case, binned):
+    n, res, log2_T, F, f16, cell = case
+    g, o = _pair(n, res, log2_T, F, f16, cell)
+    pts = _points(n, 6000, 40 + n)
+    d = inputs.gradients(len(pts), len(res) * F, 50 + n)
+    got = _gpu_bwd(g, pts, d, binned)
+    assert got.shape == g.table_shape
+    ref, mag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
+    tol = (cnt + n + 2) * 2.0 ** -24 * mag + 1e-30
+    err = np.abs(got - ref)
+    assert (err <= tol).all(), f"worst {err.max()} ; {int((err > tol).sum())} rows out of tolerance"
+    assert np.all(got[cnt == 0] == 0)
+
+
+@pytest.mark.parametrize("case", LAYOUT_CASES[:4], ids=_ids)
+def test_layout_input_grad_parity(case):
+    n, res, log2_T, F, f16, cell = case
+    g, o = _pair(n, res, log2_T, F, f16, cell)
+    pts = inputs.uniform_points(3000, n, 60 + n)   # away from the faces (one-sided derivatives there)
+    tab = _tables(g, f16, 61 + n)
+    d = inputs.gradients(len(pts), len(res) * F, 62 + n)
+    out = torch.empty((len(pts), n), dtype=torch.float32, device=DEV)
+    spx.spx_encode_input_grad(g, torch.from_numpy(pts).to(DEV), torch.from_numpy(tab).to(DEV),
+                              torch.from_numpy(d).to(DEV), out)
+    torch.cuda.synchronize()
+    ref, mag = oracle.encode_input_grad(o, pts, tab, d.astype(np.float64), with_mag=True)
+    V = n + 1 if cell == spx.SPX_SIMPLEX else 1 << n
+    tol = 2 * (F + 2 * n + V + len(res) + 8) * 2.0 ** -24 * mag + 1e-30
+    assert (np.abs(out.cpu().numpy() - ref) <= tol).all()
+
+
+@pytest.mark.parametrize("case", [LAYOUT_CASES[1], LAYOUT_CASES[2]], ids=_ids)
+def test_layout_bwd_adam_fused(case):
+    """Adjoint + Adam in one pass over dense levels (whose last bucket is a
+    partial slice) and hashed ones, against the oracle's adjoint followed by
+    its Adam step (the bounds of tests/test_gpu_encode.py)."""
+    n, res, log2_T, F, f16, cell = case
+    g, o = _pair(n, res, log2_T, F, True, cell)
+    pts = inputs.uniform_points(20001, n, 70)
+    d = inputs.gradients(len(pts), len(res) * F, 71) * 1e-3
+    shape = g.table_shape
+    rng = np.random.default_rng(72)
+    p0 = (rng.normal(size=shape) * 1e-2).astype(np.float32)
+    m0 = (rng.normal(size=shape) * 1e-3).astype(np.float32)
+    v0 = (rng.random(shape) * 1e-5 + 1e-7).astype(np.float32)
+    f32 = lambda x: float(np.float32(x))
+    lr, b1, b2, eps, step = f32(1e-2), f32(0.9), f32(0.99), f32(1e-15), 4
+    tp, tm, tv = (torch.from_numpy(a.copy()).to(DEV) for a in (p0, m0, v0))
+    th = torch.empty(shape, dtype=torch.float16, device=DEV)
+    ws = torch.empty(spx.spx_encode_bwd_workspace(g, len(pts)), dtype=torch.uint8, device=DEV)
+    spx.spx_encode_bwd_adam(g, torch.from_numpy(pts).to(DEV), torch.from_numpy(d).to(DEV), tp, tm, tv, th,
+                            lr=lr, beta1=b1, beta2=b2, eps=eps, step=step, workspace=ws)
+    torch.cuda.synchronize()
+    gref, gmag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
+    tolg = (cnt + n + 2) * 2.0 ** -24 * gmag + 1e-30
+    p, m, v, _ = oracle.adam_step(p0.ravel(), gref.ravel().astype(np.float32), m0.ravel(), v0.ravel(),
+                                  lr, b1, b2, eps, step)
+    gp, gm, gv = (t.cpu().numpy().ravel().astype(np.float64) for t in (tp, tm, tv))
+    u = 2.0 ** -24
+    G, TG = np.abs(gref.ravel()), tolg.ravel() + u * np.abs(gref.ravel())
+    tol_m = 3 * u * (b1 * np.abs(m0.ravel()) + (1 - b1) * G) + (1 - b1) * TG
+    tol_v = 4 * u * (b2 * v0.ravel() + (1 - b2) * G ** 2) + (1 - b2) * (2 * G + TG) * TG
+    bc1, bc2 = 1 - b1 ** step, 1 - b2 ** step
+    sv = np.sqrt(np.maximum(v.astype(np.float64) - tol_v, 0) / bc2) + eps
+    upd = np.abs(p0.ravel().astype(np.float64) - p)
+    tol_p = (2 * u * np.abs(p) + 10 * u * upd + lr * (tol_m / bc1) / sv + upd * 0.5 * (tol_v / bc2) / (sv * sv))
+    for name, got, ref, tol in [("m", gm, m, tol_m), ("v", gv, v, tol_v), ("p", gp, p, tol_p)]:
+        err = np.abs(got - ref)
+        assert (err <= tol).all(), f"{name}: worst err/tol {np.max(err / tol):.3f}"
+    np.testing.assert_array_equal(th.cpu().numpy().view(np.uint16).ravel(),
+                                  oracle.cast_f32_f16(gp.astype(np.float32)))
+
+
+@pytest.mark.parametrize("cell", [spx.SPX_SIMPLEX, spx.SPX_GRID])
+def test_layout_image_workload_full_size(cell):
+    """The image workload's shape (n=2, 16 levels 16..32768, T=2^22, binary16
+    tables) in the sized layout: 2^20 points; forward of 4096 sampled points
+    against the oracle; the binned adjoint against the atomic one row by row
+    (both bounded by the summation bound) and through <d, J t> = <J^T d, t>."""
+    w = inputs.IMAGE_2D
+    res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
+    g, o = _pair(2, res, w.log2_T, 2, True, cell)
+    assert g.table_shape[0] < w.n_levels << w.log2_T
+    pts = inputs.pixel_points(1 << 20, 80)
+    tab = _tables(g, True, 81)
+    got = _gpu_fwd(g, pts, tab, True)
+    sel = np.sort(np.random.default_rng(82).choice(len(pts), 4096, replace=False))
+    _check_fwd(got[sel], oracle.encode_fwd(o, pts[sel], tab), oracle.encode_fwd_absmag(o, pts[sel], tab), True)
+    d = inputs.gradients(len(pts), 32, 83)
+    a = _gpu_bwd(g, pts, d, binned=False)
+    b = _gpu_bwd(g, pts, d, binned=True)
+    fwd32 = _gpu_fwd(g, pts, tab, False)
+    lhs = float((d.astype(np.float64) * fwd32).sum())
+    rhs = float((b * tab.astype(np.float64)).sum())
+    assert abs(lhs - rhs) <= 1e-5 * float(np.abs(d.astype(np.float64) * np.abs(fwd32)).sum())
+    scale = np.abs(d.astype(np.float64)).sum(0).reshape(16, 2)
+    lay = spx.spx_table_layout(g)
+    for l in range(16):
+        r0, r1 = lay["offsets"][l], lay["offsets"][l + 1]
+        assert np.all(np.abs(a[r0:r1] - b[r0:r1]) <= 2.0 ** -24 * (len(pts) * 3 + 8) * scale[l] + 1e-30), l
