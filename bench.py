@@ -92,7 +92,13 @@ def gather_ceiling_ms(N, unique_per_wave, footprints, probe, wave=64):
 
 
 COPY_ELEMS = 1 << 26  # calibration copy: 256 MiB read, 128 MiB written
-TRAFFIC_FILE = os.path.join("profiles", "bin_accum_adam_image2d_traffic.json")
+# per workload: the traffic file of its dominant kernel ({} -> image2d / volume3d)
+TRAFFIC_FILE = os.path.join("profiles", "bin_accum_adam_{}_traffic.json")
+
+
+def _traffic_path(workload):
+    tag = "volume3d" if workload.startswith("volume") else "image2d"
+    return os.path.join(ROOT, TRAFFIC_FILE.format(tag))
 # kernels whose counters the traffic file holds, and the sources that define them
 TRAFFIC_KERNELS = {"bin_accum_adam": ("bin_accum_kernel", "true")}
 TRAFFIC_SOURCES = ["paper_2311_15439_amd/csrc/binned_accum.hpp", "paper_2311_15439_amd/csrc/spx_internal.h",
@@ -148,7 +154,7 @@ def write_traffic(read_csv, write_csv, workload):
         r = [read_bytes(c) for (_, k), c in reads if mine(k)][-1]
         w = [c["WRITE_SIZE"] * 1024.0 for (_, k), c in writes if mine(k)][-1]
         res["kernels"][name] = {"read_bytes": r, "written_bytes": w, "bytes": r + w}
-    with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as fh:
+    with open(_traffic_path(workload), "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res))
 
@@ -158,7 +164,7 @@ def measured_traffic(kernel, workload):
     no measurement for this kernel on this workload or its sources changed
     since it was taken."""
     try:
-        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
+        with open(_traffic_path(workload)) as fh:
             t = json.load(fh)
     except OSError:
         return None
@@ -177,6 +183,8 @@ def _points(w, batch):
     from paper_2311_15439_amd import inputs
     if w.name.startswith("image"):
         return inputs.pixel_points(w.n_points, w.seed_points + 1000 * batch)
+    if w.name.startswith("field"):
+        return inputs.uniform_points(w.n_points, w.n_dims, w.seed_points + 1000 * batch)
     return inputs.ray_points(w.n_points // 256, 256, w.seed_points + 1000 * batch)
 
 
@@ -184,13 +192,21 @@ def _targets(w, pts, batch):
     from paper_2311_15439_amd import inputs
     if w.name.startswith("image"):
         return inputs.procedural_rgb(pts, 4)
+    if w.name.startswith("field"):
+        return inputs.procedural_nd(pts, 60 + w.n_dims)
     return inputs.procedural_density(pts, 7)
+
+
+def _colour_target(w):
+    """Targets that are colours in [0, 1] (PSNR against peak 1, outputs
+    clamped), as opposed to the volume's density and colour."""
+    return w.name.startswith("image") or w.name.startswith("field")
 
 
 class TrainStep:
     """All device buffers of one training step; launches only library kernels."""
 
-    def __init__(self, w, cell, batches, host_tables, weights, d_out, fused=True, equal_memory=False):
+    def __init__(self, w, cell, batches, host_tables, weights, d_out, fused=True, equal_memory=False, layout=0):
         import torch
         from paper_2311_15439_amd import spx
         self.torch, self.spx = torch, spx
@@ -198,7 +214,11 @@ class TrainStep:
         self.w = w
         self.res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
         self.enc = spx.Encoding(w.n_dims, self.res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16, cell=cell,
-                                equal_memory=equal_memory)
+                                equal_memory=equal_memory, layout=layout)
+        if tuple(host_tables.shape) != self.enc.table_shape:
+            # another table layout: the same initial distribution over its rows
+            host_tables = np.random.default_rng(w.seed_tables).uniform(
+                -w.table_init, w.table_init, self.enc.table_shape).astype(np.float32)
         self.N = w.n_points
         self.batches = [(torch.from_numpy(p).to(dev), torch.from_numpy(t).to(dev)) for p, t in batches]
         self.master = torch.from_numpy(host_tables.astype(np.float32)).to(dev)
@@ -230,8 +250,8 @@ class TrainStep:
         self.t = 0
         self.lr = 1e-2
         self.fused = fused
-        # the fused encoding + network forward covers 2-/3-D fields of 16 levels x 2 features
-        self.fused_fwd = w.n_dims in (2, 3) and D == 32 and w.n_feat == 2
+        # the fused encoding + network forward covers 2-/3-D fields of 16 levels x 2 features, hashed tables
+        self.fused_fwd = w.n_dims in (2, 3) and D == 32 and w.n_feat == 2 and layout == spx.SPX_LAYOUT_HASHED
 
     @property
     def names(self):
@@ -534,7 +554,7 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
     from paper_2311_15439_amd import inputs, spx
     dev = "cuda"
     out = {}
-    wls = [inputs.IMAGE_2D, inputs.VOLUME_3D] + [inputs.sweep_workload(n) for n in range(2, 7)]
+    wls = [inputs.PLAIN_2D, inputs.IMAGE_2D, inputs.VOLUME_3D] + [inputs.sweep_workload(n) for n in range(2, 7)]
     for w in wls:
         print(f"# encode sweep: {w.name}", file=sys.stderr, flush=True)
         if w.name.startswith("volume"):
@@ -545,19 +565,27 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
             p = inputs.uniform_points(w.n_points, w.n_dims, w.seed_points)
         N = p.shape[0]
         pts = torch.from_numpy(p).to(dev)
+        # binary16 tables and features, except the plain configuration's binary32 ones
+        f16 = w.table_f16
         tab = torch.from_numpy(inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables,
-                                             True)).to(dev)
+                                             f16)).to(dev)
         D = w.n_levels * w.n_feat
         dout = torch.from_numpy(inputs.gradients(N, D, w.seed_points + 50)).to(dev)
-        feats = torch.empty((N, D), dtype=torch.float16, device=dev)
+        feats = torch.empty((N, D), dtype=torch.float16 if f16 else torch.float32, device=dev)
         grad = torch.zeros(tab.shape, dtype=torch.float32, device=dev)
         res = spx.spx_level_resolutions(w.n_min, w.growth, w.n_levels)
         row = {"points": N}
         for cell, cname in ((spx.SPX_SIMPLEX, "simplex"), (spx.SPX_GRID, "grid")):
-            enc = spx.Encoding(w.n_dims, res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16, cell=cell)
+            enc = spx.Encoding(w.n_dims, res, w.log2_T, w.n_feat, table_dtype=spx.SPX_F16 if f16 else spx.SPX_F32,
+                               cell=cell)
             ws = torch.empty(spx.spx_encode_bwd_workspace(enc, N), dtype=torch.uint8, device=dev)
+
+            def twin():
+                if f16:  # the twin covers binary16 tables
+                    spx.spx_encode_gather_twin(enc, pts, tab, feats)
+
             for _ in range(warm):
-                spx.spx_encode_gather_twin(enc, pts, tab, feats)
+                twin()
                 spx.spx_encode_fwd(enc, pts, tab, feats)
                 grad.zero_()
                 spx.spx_encode_bwd(enc, pts, dout, grad, ws)
@@ -565,7 +593,7 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
             torch.cuda.synchronize()
             for r in range(reps):
                 ev[r][0].record()
-                spx.spx_encode_gather_twin(enc, pts, tab, feats)
+                twin()
                 ev[r][1].record()
                 spx.spx_encode_fwd(enc, pts, tab, feats)
                 ev[r][2].record()
@@ -607,11 +635,12 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
             V = enc.n_vertices
             gathers = N * w.n_levels * V
             row[cname] = {"fwd": fq, "zero_grad": _quantiles(z), "bwd": _quantiles(b), "fwd_bwd": tq,
-                          "gather_twin": wq, "bwd_kernels": bwd_kernels, "input_grad_ms": input_grad_ms,
+                          "gather_twin": wq if f16 else None, "bwd_kernels": bwd_kernels,
+                          "input_grad_ms": input_grad_ms,
                           "fwd_points_per_s": N / (fq["median_ms"] * 1e-3),
                           "fwd_bwd_points_per_s": N / (tq["median_ms"] * 1e-3),
                           "fwd_gathers_per_s": gathers / (fq["median_ms"] * 1e-3),
-                          "twin_gathers_per_s": gathers / (wq["median_ms"] * 1e-3)}
+                          "twin_gathers_per_s": gathers / (wq["median_ms"] * 1e-3) if f16 else None}
             if ceil:
                 row[cname]["gather_ceiling"] = ceil
                 row[cname]["fwd_gather_frac"] = ceil["ceiling_ms"] / fq["median_ms"]
@@ -625,14 +654,19 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
     return out
 
 
-def equal_accuracy(w, host_tables, weights, d_out, steps=2000, n_train=6):
-    """Accuracy at equal memory: train the field with the simplex encoding
-    (equal-memory level scaling on) and with the 2^n grid for the same number
-    of steps on the same batches, then compare the PSNR on a held-out batch
-    (image: RGB clamped to [0, 1], peak 1; volume: density and colour,
+EQUAL_ACCURACY_VARIANTS = (("simplex_equal_memory", 0, True, 0), ("simplex", 0, False, 0), ("grid", 1, False, 0))
+
+
+def equal_accuracy(w, host_tables, weights, d_out, steps=2000, n_train=6, variants=EQUAL_ACCURACY_VARIANTS):
+    """Accuracy at equal memory: train the field with each variant (name,
+    cell, equal-memory level scaling, table layout) for the same number of
+    steps on the same batches, then compare the PSNR on a held-out batch
+    (colour targets: clamped to [0, 1], peak 1; volume: density and colour,
     peak = the largest held-out target value).  Adam's step size decays
     from 1e-2 to 1e-3 over the run, so the end point is not dominated by
-    step noise."""
+    step noise.  Also reported per variant: the mean training step time over
+    the run and the table's rows and bytes (binary16 copy; the binary32
+    master and Adam's two moments are 6 times that)."""
     import torch
     from paper_2311_15439_amd import spx
     batches = []
@@ -641,26 +675,69 @@ def equal_accuracy(w, host_tables, weights, d_out, steps=2000, n_train=6):
         batches.append((p, _targets(w, p, 100 + b)))
     held_p, held_t = batches.pop()
     out = {"steps": steps, "train_batches": n_train, "points_per_step": w.n_points}
-    for cell, em, name in ((spx.SPX_SIMPLEX, True, "simplex_equal_memory"), (spx.SPX_SIMPLEX, False, "simplex"),
-                           (spx.SPX_GRID, False, "grid")):
-        print(f"# equal accuracy: training {name} for {steps} steps", file=sys.stderr, flush=True)
-        ts = TrainStep(w, cell, batches, host_tables, weights, d_out, equal_memory=em)
+    for name, cell, em, layout in variants:
+        print(f"# accuracy {w.name}: training {name} for {steps} steps", file=sys.stderr, flush=True)
+        ts = TrainStep(w, cell, batches, host_tables, weights, d_out, equal_memory=em, layout=layout)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
         for i in range(steps):
             ts.lr = 1e-2 * 0.1 ** (i / steps)  # exponential decay to 1e-3: a settled end point
             ts.step(i)
+        ev[1].record()
         hp = torch.from_numpy(held_p).to("cuda")
         ht = torch.from_numpy(held_t).to("cuda")
         spx.spx_encode_fwd(ts.enc, hp, ts.tab16, ts.feats)
         spx.spx_mlp_fwd(ts.mlp, ts.feats, *ts.Wv, ts.y)
-        if w.name.startswith("image"):
+        if _colour_target(w):
             mse, peak = torch.mean((ts.y.clamp(0, 1) - ht) ** 2).item(), 1.0
         else:
             mse, peak = torch.mean((ts.y - ht) ** 2).item(), float(held_t.max())
-        out[name] = {"psnr_db": 10.0 * np.log10(peak * peak / mse), "mse": mse}
+        rows = int(np.prod(ts.enc.table_shape)) // w.n_feat
+        out[name] = {"psnr_db": 10.0 * np.log10(peak * peak / mse), "mse": mse,
+                     "ms_per_step": ev[0].elapsed_time(ev[1]) / steps, "table_rows": rows,
+                     "table_f16_MiB": rows * w.n_feat * 2 / 2 ** 20}
         del ts
         torch.cuda.empty_cache()
-    out["simplex_minus_grid_db"] = out["simplex"]["psnr_db"] - out["grid"]["psnr_db"]
-    out["simplex_equal_memory_minus_grid_db"] = out["simplex_equal_memory"]["psnr_db"] - out["grid"]["psnr_db"]
+    names = [v[0] for v in variants]
+    if "grid" in names:
+        for nm in names:
+            if nm != "grid":
+                out[f"{nm}_minus_grid_db"] = out[nm]["psnr_db"] - out["grid"]["psnr_db"]
+                out[f"{nm}_speedup"] = out["grid"]["ms_per_step"] / out[nm]["ms_per_step"]
+    return out
+
+
+def nd_accuracy(dims=(3, 4, 5, 6), steps=1000):
+    """Beyond three dimensions: an n-dimensional colour field (inputs.
+    nd_workload: 16 levels 16..512, T = 2^20, 2^18 points per step, MLP
+    32-64-64-3) trained with the simplex (plain and equal-memory) and the
+    2^n grid; held-out PSNR and training step time for each."""
+    from paper_2311_15439_amd import inputs
+    out = {}
+    for n in dims:
+        w = inputs.nd_workload(n)
+        host_tables = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, False)
+        weights = inputs.mlp_weights(w.n_levels * w.n_feat, 64, 3, 9)
+        out[w.name] = equal_accuracy(w, host_tables, weights, 3, steps=steps, n_train=4)
+    return out
+
+
+def layout_accuracy(steps=2000):
+    """Sec. 5.2's table sizing: the image and volume workloads trained with
+    every level hashed into T rows (the paper's configurations) and with the
+    sized layout (dense coarse levels, hashed levels sized by the simplex's
+    used share); held-out PSNR, table memory and step time."""
+    from paper_2311_15439_amd import inputs, spx
+    out = {}
+    for w, d_out in ((inputs.IMAGE_2D, 3), (inputs.VOLUME_3D, 4)):
+        host_tables = inputs.tables(w.n_levels, 1 << w.log2_T, w.n_feat, w.table_init, w.seed_tables, False)
+        weights = inputs.mlp_weights(w.n_levels * w.n_feat, 64, d_out, 9)
+        out[w.name] = equal_accuracy(w, host_tables, weights, d_out, steps=steps, n_train=4,
+                                     variants=(("hashed", spx.SPX_SIMPLEX, False, spx.SPX_LAYOUT_HASHED),
+                                               ("sized", spx.SPX_SIMPLEX, False, spx.SPX_LAYOUT_SIZED)))
+        r = out[w.name]
+        r["sized_memory_fraction"] = r["sized"]["table_rows"] / r["hashed"]["table_rows"]
+        r["sized_minus_hashed_db"] = r["sized"]["psnr_db"] - r["hashed"]["psnr_db"]
     return out
 
 
@@ -969,6 +1046,10 @@ def main():
                     help="skip the volume workload's training step (simplex vs grid) and its accuracy comparison")
     ap.add_argument("--no-render", action="store_true",
                     help="skip the volume-rendering training step (compositing along rays), simplex vs grid")
+    ap.add_argument("--no-nd", action="store_true",
+                    help="skip the n-dimensional accuracy and step-time comparison (n = 3..6), simplex vs grid")
+    ap.add_argument("--no-layout", action="store_true",
+                    help="skip the table-layout comparison (hashed vs sized tables: accuracy, memory)")
     ap.add_argument("--detail-out", default=DETAIL_DEFAULT,
                     help="file for the full JSON record (the last stdout line is a compact summary)")
     ap.add_argument("--pmc-pass", action="store_true",
@@ -976,7 +1057,7 @@ def main():
                          "(the program profiled by the rocprofv3 --pmc traffic runs)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("READ_CSV", "WRITE_CSV"),
                     help="turn the counter CSVs of the two --pmc runs (of --pmc-pass on --workload) into "
-                         + TRAFFIC_FILE + " and exit")
+                         + TRAFFIC_FILE.format("<workload>") + " and exit")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic, _workload(args.workload).name)
@@ -1056,6 +1137,12 @@ def main():
     if not args.no_render and w.name.startswith("image"):
         render = render_bench()
 
+    nd, layout = None, None
+    if not args.no_nd:
+        nd = nd_accuracy()
+    if not args.no_layout:
+        layout = layout_accuracy()
+
     sweep, probe = None, None
     if not args.no_sweep:
         print("# random-gather probe", file=sys.stderr, flush=True)
@@ -1101,6 +1188,8 @@ def main():
         "gather_probe_gathers_per_s": probe,
         "encode_sweep": sweep,
         "equal_accuracy": accuracy,
+        "nd_accuracy": nd,
+        "layout_accuracy": layout,
         "volume_step": volume,
         "render_step": render,
         "serving": serving,
@@ -1142,11 +1231,29 @@ def summary_lines(d):
     for name, a in acc.items():
         out.append(f"# accuracy {name}: PSNR simplex {a['simplex']['psnr_db']:.2f}, equal-memory "
                    f"{a['simplex_equal_memory']['psnr_db']:.2f}, grid {a['grid']['psnr_db']:.2f} dB")
+    for name, a in (d.get("nd_accuracy") or {}).items():
+        out.append(f"# accuracy {name}: PSNR simplex {a['simplex']['psnr_db']:.2f}, equal-memory "
+                   f"{a['simplex_equal_memory']['psnr_db']:.2f}, grid {a['grid']['psnr_db']:.2f} dB; step "
+                   f"{a['simplex']['ms_per_step']:.3f} / {a['grid']['ms_per_step']:.3f} ms (simplex / grid)")
+    for name, a in (d.get("layout_accuracy") or {}).items():
+        out.append(f"# table layout {name}: sized tables {a['sized_memory_fraction']:.3f} of the hashed rows, PSNR "
+                   f"{a['sized']['psnr_db']:.2f} vs {a['hashed']['psnr_db']:.2f} dB")
     sv = d.get("serving")
     if sv:
         loads = ", ".join(f"{l['load']:.0%}: p50 {l['p50_ms']:.2f} p99 {l['p99_ms']:.2f} ms" for l in sv["loads"])
         out.append(f"# serving: saturation {sv['saturation_points_per_s'] / 1e6:.0f} M points/s; {loads}")
     return out
+
+
+# what one timed step of each workload is, for the headline line
+STEP_WORKLOADS = {
+    "image-2d n=2 L=16 T=2^22 F=2 f16":
+        ("image-2d training step: n=2, L=16, T=2^22, F=2 f16 tables, N_l 16..32768, "
+         "2^20 random pixels of a 16384^2 image per step, MLP 32-64-64-3, Adam"),
+    "volume-3d n=3 L=16 T=2^19 F=2 f16":
+        ("volume-3d training step: n=3, L=16, T=2^19, F=2 f16 tables, N_l 16..2048, "
+         "2^13 rays x 256 samples per step, MLP 32-64-64-4, Adam"),
+}
 
 
 def headline(d, value, steps, warmup, detail_path):
@@ -1167,8 +1274,7 @@ def headline(d, value, steps, warmup, detail_path):
         "vs_baseline": None,
         "dtype": "f16 tables+features, f32 accumulate; MLP f16 MFMA fwd, bf16 MFMA operands bwd",
         "data": "synthetic",
-        "config": {"workload": ("image-2d training step: n=2, L=16, T=2^22, F=2 f16 tables, N_l 16..32768, "
-                                "2^20 random pixels of a 16384^2 image per step, MLP 32-64-64-3, Adam"),
+        "config": {"workload": STEP_WORKLOADS.get(d["config"]["workload"], d["config"]["workload"]),
                    "parallelism": "single GPU"},
         "roofline": {"bound": rf["bound"], "kernel": rf["kernel"], "achieved": _r(rf["achieved"]),
                      "peak": rf["peak"], "unit": rf["unit"], "frac": _r(rf["frac"]),
@@ -1206,6 +1312,19 @@ def headline(d, value, steps, warmup, detail_path):
     if acc:
         acc["cols"] = ["simplex_minus_grid_db", "equal_memory_minus_grid_db"]
         line["accuracy"] = acc
+    nd = d.get("nd_accuracy")
+    if nd:
+        line["nd_accuracy"] = {"cols": ["simplex_minus_grid_db", "equal_memory_minus_grid_db", "simplex_step_speedup"]}
+        for name, a in nd.items():
+            line["nd_accuracy"][name.split(" L=")[0]] = [_r(a["simplex_minus_grid_db"], 3),
+                                                         _r(a["simplex_equal_memory_minus_grid_db"], 3),
+                                                         _r(a["simplex_speedup"], 3)]
+    lay = d.get("layout_accuracy")
+    if lay:
+        line["table_layout"] = {"cols": ["sized_memory_fraction", "sized_minus_hashed_db"]}
+        for name, a in lay.items():
+            line["table_layout"][name.split(" ")[0]] = [_r(a["sized_memory_fraction"], 3),
+                                                        _r(a["sized_minus_hashed_db"], 3)]
     sv = d.get("serving")
     if sv:
         line["serving"] = {"saturation_points_per_s": _r(sv["saturation_points_per_s"]),

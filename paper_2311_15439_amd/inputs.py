@@ -159,3 +159,35 @@ def procedural_density(pts: np.ndarray, seed: int, n_blobs: int = 32) -> np.ndar
         rgb += g[:, None] * col[b]
     rgb /= np.maximum(sig, 1e-6)[:, None]
     return np.concatenate([sig[:, None], rgb], 1).astype(np.float32)
+
+
+def nd_workload(n: int) -> Workload:
+    """An n-dimensional regression field for the accuracy comparison beyond
+    three dimensions (standing in for the high-dimensional tasks of Sec. 6):
+    16 levels of 2 features (the network's 32 inputs), resolutions
+    16 -> 512, T = 2^20, 2^18 points per step."""
+    return Workload(f"field n={n} L=16 T=2^20 F=2 f16", n, 16, 20, 2, True, 16.0,
+                    growth_from_ends(16, 512, 16), 1 << 18, 1e-4, 40 + n, 50 + n)
+
+
+def procedural_nd(pts: np.ndarray, seed: int, n_blobs: int = 48, n_waves: int = 6) -> np.ndarray:
+    """Synthetic 3-channel target over [0,1]^n: a 0.25 base, anisotropic
+    Gaussian blobs (widths 2^-4 .. 2^-2 per axis) and plane waves of up to
+    24 cycles per unit, clipped to [0, 1]."""
+    rng = np.random.default_rng(seed)
+    n = pts.shape[1]
+    c = rng.random((n_blobs, n))
+    s = np.exp(rng.uniform(np.log(2.0 ** -4), np.log(2.0 ** -2), (n_blobs, n)))
+    col = rng.random((n_blobs, 3))
+    om = rng.normal(size=(n_waves, n))
+    om *= (rng.uniform(2, 24, (n_waves, 1)) * 2 * np.pi / np.linalg.norm(om, axis=1, keepdims=True))
+    ph = rng.uniform(0, 2 * np.pi, n_waves)
+    wc = rng.random((n_waves, 3)) * 0.2
+    x = pts.astype(np.float64)
+    out = np.full((len(x), 3), 0.25)
+    for b in range(n_blobs):
+        r2 = (((x - c[b]) / s[b]) ** 2).sum(1)
+        out += np.exp(-0.5 * r2)[:, None] * col[b]
+    for k in range(n_waves):
+        out += np.sin(x @ om[k] + ph[k])[:, None] * wc[k]
+    return np.clip(out, 0.0, 1.0).astype(np.float32)

@@ -14,11 +14,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_traffic_tied_to_workload_and_sources(tmp_path, monkeypatch):
     # a traffic file written for the image workload with the current sources
-    path = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic{}.json"))
+    path = tmp_path / "trafficimage2d.json"
     rec = {"sources_sha256": bench._sources_digest(), "workload": inputs.IMAGE_2D.name,
            "kernels": {"bin_accum_adam": {"bytes": 123.0}}}
     path.write_text(json.dumps(rec))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
     assert bench.measured_traffic("bin_accum_adam", inputs.IMAGE_2D.name) == 123.0
     assert bench.measured_traffic("bin_accum_adam", inputs.VOLUME_3D.name) is None
     assert bench.measured_traffic("bin_scatter", inputs.IMAGE_2D.name) is None
@@ -27,7 +27,7 @@ def test_traffic_tied_to_workload_and_sources(tmp_path, monkeypatch):
     path.write_text(json.dumps(rec))
     assert bench.measured_traffic("bin_accum_adam", inputs.IMAGE_2D.name) is None
     # no file
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing{}.json"))
     assert bench.measured_traffic("bin_accum_adam", inputs.IMAGE_2D.name) is None
 
 
@@ -44,8 +44,8 @@ def test_write_traffic_from_request_sizes(tmp_path, monkeypatch):
         + f'12,"spx::cast_kernel(y)",WRITE_SIZE,{bench.COPY_ELEMS * 2 / 1024.0}\n'
     (tmp_path / "r.csv").write_text(rd)
     (tmp_path / "w.csv").write_text(wr)
-    out = tmp_path / "t.json"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    out = tmp_path / "timage2d.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "t{}.json"))
     bench.write_traffic(str(tmp_path / "r.csv"), str(tmp_path / "w.csv"), inputs.IMAGE_2D.name)
     t = json.loads(out.read_text())
     k = t["kernels"]["bin_accum_adam"]
@@ -110,6 +110,7 @@ def _fake_detail():
            "simplex_minus_grid_db": -0.3, "simplex_equal_memory_minus_grid_db": -0.2}
     return {
         "ms_per_step": 1.652,
+        "config": {"workload": inputs.IMAGE_2D.name},
         "roofline": {"bound": "hbm", "kernel": "bin_accum_adam", "achieved": 5150.123456, "peak": 8000.0,
                      "unit": "GB/s", "frac": 0.6437654, "traffic": 3.943e9, "avg_ms": 0.766, "bytes_per_launch": 3.94e9},
         "cpu_baseline": {"value": 5960.0, "unit": "points/s", "cores": 16, "kind": "oracle", "sample": "x" * 300,
@@ -118,6 +119,14 @@ def _fake_detail():
         "encode_sweep": sweep,
         "equal_accuracy": {inputs.IMAGE_2D.name: acc},
         "volume_step": {"simplex": {"points_per_s": 8.5e8}, "simplex_speedup": 1.94, "equal_accuracy": acc},
+        "nd_accuracy": {inputs.nd_workload(n).name: dict(acc, simplex={"psnr_db": 30.0, "ms_per_step": 1.0},
+                                                         simplex_equal_memory={"psnr_db": 29.0, "ms_per_step": 1.0},
+                                                         grid={"psnr_db": 30.5, "ms_per_step": 4.0},
+                                                         simplex_speedup=4.0)
+                        for n in range(3, 7)},
+        "layout_accuracy": {w.name: {"hashed": {"psnr_db": 22.9}, "sized": {"psnr_db": 22.8},
+                                     "sized_memory_fraction": 0.43, "sized_minus_hashed_db": -0.1}
+                            for w in (inputs.IMAGE_2D, inputs.VOLUME_3D)},
         "serving": {"saturation_points_per_s": 4.2e8,
                     "loads": [{"load": 0.5, "p50_ms": 1.4, "p99_ms": 5.2, "points_per_s": 2e8},
                               {"load": 0.8, "p50_ms": 2.1, "p99_ms": 5.2, "points_per_s": 3.3e8}]},
@@ -133,7 +142,9 @@ def test_headline_is_compact_json():
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
               "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
         assert k in back
-    assert "workload" in back["config"] and "bf16" in back["dtype"]
+    assert back["config"]["workload"].startswith("image-2d training step") and "bf16" in back["dtype"]
+    d["config"]["workload"] = "volume-3d n=3 L=16 T=2^19 F=2 f16"
+    assert bench.headline(d, 8e8, 20, 5, "x")["config"]["workload"].startswith("volume-3d training step")
     r = back["roofline"]
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and 0 < r["frac"] <= 1
     assert back["cpu_baseline"]["cores"] == 16 and back["cpu_baseline"]["cpu_model"]
