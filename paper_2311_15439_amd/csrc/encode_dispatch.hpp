@@ -18,19 +18,33 @@ inline unsigned grid_for(int64_t N) {
 template <class Tag, int D>
 constexpr int vertices() { return Tag::simplex ? D + 1 : (1 << D); }
 
+template <class Tag, int D, int F, typename TT, typename OT>
+void launch_fwd(const EncodeCall& c) {
+    const TT* tab = (const TT*)c.tables;
+    OT* out = (OT*)c.out;
+    const LevelGroups lg = fwd_level_groups(c.lv, D, F * (int)sizeof(TT), c.N);
+    if (lg.n > 0) {
+        const uint32_t chunks = (uint32_t)((c.N + kBlock - 1) / kBlock);
+        encode_fwd_levels_kernel<Tag, D, F, TT, OT><<<dim3(chunks * (uint32_t)lg.n), dim3(kBlock), 0, c.stream>>>(
+            c.N, c.pts, tab, out, c.lv, lg, chunks);
+    } else {
+        encode_fwd_kernel<Tag, D, F, TT, OT><<<dim3(grid_for(c.N)), dim3(kBlock), 0, c.stream>>>(c.N, c.pts, tab, out,
+                                                                                                 c.lv);
+    }
+}
+
 template <class Tag, int D, int F>
 hipError_t fwd_dispatch_types(const EncodeCall& c) {
-    dim3 g(grid_for(c.N)), b(kBlock);
     const double per_pt = 4.0 * D + (double)c.lv.L * F * (vertices<Tag, D>() * (c.table_f16 ? 2 : 4) + (c.out_f16 ? 2 : 4));
     trace_begin(c.stream, "encode_fwd", per_pt * (double)c.N);
     if (c.table_f16 && c.out_f16)
-        encode_fwd_kernel<Tag, D, F, f16, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (f16*)c.out, c.lv);
+        launch_fwd<Tag, D, F, f16, f16>(c);
     else if (c.table_f16)
-        encode_fwd_kernel<Tag, D, F, f16, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const f16*)c.tables, (float*)c.out, c.lv);
+        launch_fwd<Tag, D, F, f16, float>(c);
     else if (c.out_f16)
-        encode_fwd_kernel<Tag, D, F, float, f16><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (f16*)c.out, c.lv);
+        launch_fwd<Tag, D, F, float, f16>(c);
     else
-        encode_fwd_kernel<Tag, D, F, float, float><<<g, b, 0, c.stream>>>(c.N, c.pts, (const float*)c.tables, (float*)c.out, c.lv);
+        launch_fwd<Tag, D, F, float, float>(c);
     trace_end(c.stream);
     return hipGetLastError();
 }

@@ -143,6 +143,28 @@ constexpr int kBlock = 256;
 
 // ---- forward ------------------------------------------------------------
 
+// Features of one point at one level: the weighted sum of its vertices'
+// rows (binary32 accumulation, weights in vertex order).
+template <class Tag, int D, int F, typename TT, typename OT>
+__device__ __forceinline__ void encode_level(const float (&y)[D], int l, const TT* __restrict__ tables,
+                                             OT* __restrict__ orow, const LevelArgs& lv) {
+    const TT* __restrict__ tab = tables + lv.off[l] * F;
+    float acc[F];
+#pragma unroll
+    for (int j = 0; j < F; ++j) acc[j] = 0.0f;
+    visit_level(Tag{}, y, lv.sigma[l], lv.rule(l), [&](const auto& h, const auto& w, int) {
+        constexpr int K = sizeof(w) / sizeof(float);
+        float v[K][F];
+#pragma unroll
+        for (int k = 0; k < K; ++k) RowIO<TT, F>::load(tab + (size_t)h[k] * F, v[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int j = 0; j < F; ++j) acc[j] = __builtin_fmaf(w[k], v[k][j], acc[j]);
+    });
+    RowIO<OT, F>::store(orow + l * F, acc);
+}
+
 template <class Tag, int D, int F, typename TT, typename OT>
 __global__ __launch_bounds__(kBlock) void encode_fwd_kernel(int64_t N, const float* __restrict__ pts,
                                                             const TT* __restrict__ tables, OT* __restrict__ out,
@@ -154,24 +176,32 @@ __global__ __launch_bounds__(kBlock) void encode_fwd_kernel(int64_t N, const flo
         OT* __restrict__ orow = out + pt * (int64_t)(lv.L * F);
         // unrolled so that several levels' gathers are in flight together
 #pragma unroll 4
-        for (int l = 0; l < lv.L; ++l) {
-            const TT* __restrict__ tab = tables + lv.off[l] * F;
-            float acc[F];
-#pragma unroll
-            for (int j = 0; j < F; ++j) acc[j] = 0.0f;
-            visit_level(Tag{}, y, lv.sigma[l], lv.rule(l), [&](const auto& h, const auto& w, int) {
-                constexpr int K = sizeof(w) / sizeof(float);
-                float v[K][F];
-#pragma unroll
-                for (int k = 0; k < K; ++k) RowIO<TT, F>::load(tab + (size_t)h[k] * F, v[k]);
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-#pragma unroll
-                    for (int j = 0; j < F; ++j) acc[j] = __builtin_fmaf(w[k], v[k][j], acc[j]);
-            });
-            RowIO<OT, F>::store(orow + l * F, acc);
-        }
+        for (int l = 0; l < lv.L; ++l) encode_level<Tag, D, F, TT, OT>(y, l, tables, orow, lv);
     }
+}
+
+// Level-major forward.  When the levels' tables together exceed an XCD's
+// L2 but each group of consecutive levels fits, the grid is ordered group
+// by group: blocks [g * chunks, (g + 1) * chunks) encode levels
+// [first[g], first[g + 1]) of all points, one point per thread.  Blocks
+// start in index order, so the blocks in flight work on one group (two at
+// its boundary) and each XCD's L2 holds that group's rows instead of a slice
+// of every level's.  Each point is read once per group; the features are
+// the same bits as the all-levels kernel's.
+template <class Tag, int D, int F, typename TT, typename OT>
+__global__ __launch_bounds__(kBlock) void encode_fwd_levels_kernel(int64_t N, const float* __restrict__ pts,
+                                                                   const TT* __restrict__ tables,
+                                                                   OT* __restrict__ out, LevelArgs lv,
+                                                                   LevelGroups lg, uint32_t chunks) {
+    const uint32_t g = blockIdx.x / chunks;
+    const int64_t pt = (int64_t)(blockIdx.x - g * chunks) * kBlock + threadIdx.x;
+    if (pt >= N) return;
+    float y[D];
+    load_point<Tag, D>(pts, pt, lv.Fn, y);
+    OT* __restrict__ orow = out + pt * (int64_t)(lv.L * F);
+    const int l1 = lg.first[g + 1];
+#pragma unroll 2
+    for (int l = lg.first[g]; l < l1; ++l) encode_level<Tag, D, F, TT, OT>(y, l, tables, orow, lv);
 }
 
 // ---- gather twin (measurement reference) -------------------------------
