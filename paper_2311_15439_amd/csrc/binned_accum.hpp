@@ -63,7 +63,7 @@ __device__ __forceinline__ void lds_add_row(float* row, const float (&v)[F]) {
 }
 
 constexpr int kAccBlock = 1024;  // one workgroup per CU (128 KiB accumulator)
-constexpr int kAccUnroll = 2;
+constexpr int kAccUnroll = 1;
 
 // Adam update of four parameters with their summed gradients (the same
 // binary32 operation sequence as the standalone Adam kernel).
@@ -101,6 +101,19 @@ __device__ __forceinline__ void lds_add_wave(float* acc, bool ok, uint32_t slot,
     if (ok && run_last(heads)) lds_add_row<F>(&acc[slot * F], v);
 }
 
+// The same update of one entry, in place (binary32 state, optional binary16
+// copy of the parameter).
+__device__ __forceinline__ void adam1(const AdamArgs& a, float g, size_t i) {
+#pragma clang fp contract(off)
+    const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
+    const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+    const float p = a.param[i] - a.lr * (m * a.inv_bc1) / (sqrtf(v * a.inv_bc2) + a.eps);
+    a.m[i] = m;
+    a.v[i] = v;
+    a.param[i] = p;
+    if (a.param_f16) ((f16*)a.param_f16)[i] = (f16)p;
+}
+
 // A bucket's records are stored in point order, so runs of records for one
 // slot come from coherent points.
 template <int F>
@@ -115,10 +128,13 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
                                                               AdamArgs adam) {
     extern __shared__ __attribute__((aligned(16))) float acc[];
     const int S = 1 << plan.s_log2;
-    const int b = blockIdx.x;
-    int l = plan.l0;  // the level whose buckets hold b (uniform over the workgroup)
-    while (l + 1 < plan.l1 && b >= plan.boff[l + 1]) ++l;
-    const int slice = b - plan.boff[l];
+    int l = plan.l0;  // the level this workgroup works on (uniform over the workgroup)
+    while (l + 1 < plan.l1 && (int)blockIdx.x >= plan.voff[l + 1]) ++l;
+    // bucket `slice` of level l; a split bucket's workgroups take parts of it
+    const int K = plan.ks[l];
+    const int local = (int)blockIdx.x - plan.voff[l];
+    const int slice = local / K, part = local - slice * K;
+    const int b = plan.boff[l] + slice;
     // slots of this bucket: a whole 2^s slice, or the rest of a level whose
     // rows are not a multiple of it (a densely stored level)
     const int64_t left = (int64_t)lv.rows[l] - (int64_t)slice * S;
@@ -126,7 +142,8 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
     const size_t off = ((size_t)lv.off[l] + (size_t)slice * S) * F;
     const int n4 = cnt * F / 4;
     const float* base_ptr = ADAM ? adam.param : d_tables;
-    const bool vec = n4 * 4 == cnt * F && ((uintptr_t)(base_ptr + off) & 15) == 0 && n4 <= kAccPre * kAccBlock;
+    const bool vec = K == 1 && n4 * 4 == cnt * F && ((uintptr_t)(base_ptr + off) & 15) == 0 &&
+                     n4 <= kAccPre * kAccBlock;
     // The slice's state does not depend on the records: issue its loads first
     // so they overlap the record phase.
     f32x4 P[kAccPre], M[kAccPre], Vv[kAccPre];
@@ -148,7 +165,7 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
     __syncthreads();
     // privatised level: pick up the dense sums whose slot falls in this bucket
     // (a densely stored level numbers its rows over the same box)
-    if (l < plan.P) {
+    if (l < plan.P && part == 0) {
         const int ext = plan.ext[l];
         const SlotRule rule = lv.rule(l);
         const uint32_t want = (uint32_t)slice, smask = (uint32_t)S - 1u;
@@ -173,7 +190,12 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
         }
     }
     const BinRec<F>* __restrict__ recs = reinterpret_cast<const BinRec<F>*>(plan.recs);
-    const uint32_t r0 = plan.base[b], r1 = plan.base[b + 1];
+    uint32_t r0 = plan.base[b], r1 = plan.base[b + 1];
+    if (K > 1) {  // part `part` of K equal parts of the bucket's records
+        const uint64_t n = r1 - r0;
+        r1 = r0 + (uint32_t)(n * (uint64_t)(part + 1) / (uint64_t)K);
+        r0 = r0 + (uint32_t)(n * (uint64_t)part / (uint64_t)K);
+    }
     // several records in flight per thread before their LDS adds; the loop
     // bounds are uniform over the workgroup (lanes past the end idle)
     for (uint32_t rb = r0; rb < r1; rb += kAccUnroll * kAccBlock) {
@@ -189,6 +211,11 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
         for (int u = 0; u < kAccUnroll; ++u) add_record_wave<F>(acc, ok[u], rec[u]);
     }
     __syncthreads();
+    if (K > 1) {  // a part of a split bucket: its sums go to its partial slice
+        float* __restrict__ dst = plan.split + (size_t)(plan.soff[l] + (int64_t)slice * K + part) * ((size_t)F << plan.s_log2);
+        for (int i = threadIdx.x; i < cnt * F; i += kAccBlock) dst[i] = acc[i];
+        return;
+    }
     if (vec) {
 #pragma unroll
         for (int c = 0; c < kAccPre; ++c) {
@@ -209,19 +236,39 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
     } else {
         for (int i = threadIdx.x; i < cnt * F; i += kAccBlock) {
             const float g = acc[i];
-            if constexpr (!ADAM) {
+            if constexpr (!ADAM)
                 d_tables[off + i] += g;
-            } else {
-#pragma clang fp contract(off)
-                const float m = adam.b1 * adam.m[off + i] + (1.0f - adam.b1) * g;
-                const float v = adam.b2 * adam.v[off + i] + (1.0f - adam.b2) * g * g;
-                const float p = adam.param[off + i] - adam.lr * (m * adam.inv_bc1) / (sqrtf(v * adam.inv_bc2) + adam.eps);
-                adam.m[off + i] = m;
-                adam.v[off + i] = v;
-                adam.param[off + i] = p;
-                if (adam.param_f16) ((f16*)adam.param_f16)[off + i] = (f16)p;
-            }
+            else
+                adam1(adam, g, off + i);
         }
+    }
+}
+
+// Second pass over the split buckets: each entry's partial sums added in
+// part order (the result does not depend on scheduling), then the same
+// update as an unsplit bucket's.  kSplitChunks workgroups per bucket.
+constexpr int kSplitBlock = 256, kSplitChunks = 32;
+template <int F, bool ADAM>
+__global__ __launch_bounds__(kSplitBlock) void bin_split_finish_kernel(BinPlan plan, LevelArgs lv,
+                                                                      float* __restrict__ d_tables, AdamArgs adam) {
+    const int S = 1 << plan.s_log2;
+    const int sb = (int)blockIdx.x / kSplitChunks, c = (int)blockIdx.x - sb * kSplitChunks;
+    int l = plan.l0;  // levels without split buckets have sboff[l + 1] == sboff[l]
+    while (l + 1 < plan.l1 && sb >= plan.sboff[l + 1]) ++l;
+    const int K = plan.ks[l];
+    const int slice = sb - plan.sboff[l];
+    const int64_t left = (int64_t)lv.rows[l] - (int64_t)slice * S;
+    const int cnt = left < S ? (int)left : S;
+    const size_t off = ((size_t)lv.off[l] + (size_t)slice * S) * F;
+    const size_t stride = (size_t)F << plan.s_log2;
+    const float* __restrict__ src = plan.split + (size_t)(plan.soff[l] + (int64_t)slice * K) * stride;
+    for (int i = c * kSplitBlock + threadIdx.x; i < cnt * F; i += kSplitChunks * kSplitBlock) {
+        float g = src[i];
+        for (int k = 1; k < K; ++k) g += src[(size_t)k * stride + i];
+        if constexpr (!ADAM)
+            d_tables[off + i] += g;
+        else
+            adam1(adam, g, off + i);
     }
 }
 
@@ -235,10 +282,16 @@ hipError_t launch_accum(const EncodeCall& c, const BinPlan& p, double payload) {
     const size_t lds = (size_t)(F << p.s_log2) * sizeof(float);
     if (c.adam.param) {
         trace_begin(c.stream, "bin_accum_adam", payload + slots * (c.adam.param_f16 ? 26.0 : 24.0));
-        bin_accum_kernel<D, F, true><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv, nullptr, c.adam);
+        bin_accum_kernel<D, F, true><<<p.VB, kAccBlock, lds, c.stream>>>(p, c.lv, nullptr, c.adam);
+        if (p.nsplit > 0)
+            bin_split_finish_kernel<F, true><<<p.nsplit * kSplitChunks, kSplitBlock, 0, c.stream>>>(p, c.lv, nullptr,
+                                                                                                  c.adam);
     } else {
         trace_begin(c.stream, "bin_accum", payload + slots * 8.0);
-        bin_accum_kernel<D, F, false><<<p.B, kAccBlock, lds, c.stream>>>(p, c.lv, c.d_tables, c.adam);
+        bin_accum_kernel<D, F, false><<<p.VB, kAccBlock, lds, c.stream>>>(p, c.lv, c.d_tables, c.adam);
+        if (p.nsplit > 0)
+            bin_split_finish_kernel<F, false><<<p.nsplit * kSplitChunks, kSplitBlock, 0, c.stream>>>(p, c.lv,
+                                                                                                   c.d_tables, c.adam);
     }
     trace_end(c.stream);
     return hipGetLastError();

@@ -133,11 +133,18 @@ struct BinPlan {
     int ext[32];      // dense box extent per privatised level
     int doff[33];     // first dense entry of each privatised level
     int boff[33];     // first bucket of level l in the group (levels l0..l1)
+    int ks[32];       // workgroups sharing each bucket of level l (1: not split)
+    int voff[33];     // first accumulation workgroup of level l (levels l0..l1)
+    int VB;           // accumulation workgroups of the group
+    int sboff[33];    // first split bucket of level l (counting split buckets only)
+    int nsplit;       // split buckets of the group
+    int64_t soff[33]; // first partial slice of level l in `split`
     uint32_t* counts;  // [W][B]
     uint32_t* base;    // [B + 1]
     void* recs;        // records
     float* partial;    // [W][Dtot * F] per-workgroup dense sums
     float* gdense;     // [Dtot * F] their total
+    float* split;      // partial slices of split buckets, 2^s * F floats each
 };
 
 // Sizes shared by every group; a pure function of the encoding's level
@@ -148,8 +155,9 @@ struct BinLayout {
     int gl[33];       // group g holds levels [gl[g], gl[g + 1])
     int ext[32];
     int doff[33];
+    int ks[32];       // workgroups sharing each bucket of level l
     int64_t N, chunk;
-    size_t off_counts, off_base, off_totals, off_recs, off_partial, off_gdense, total_bytes;
+    size_t off_counts, off_base, off_totals, off_recs, off_partial, off_gdense, off_split, total_bytes;
     bool ok;
 };
 
@@ -223,6 +231,34 @@ inline BinLayout bin_layout(int D, int F, int64_t N, bool simplex, const LevelAr
         b.P = q + 1;
         b.doff[q + 1] = b.Dtot;
     }
+    // Split buckets.  One workgroup sums a bucket, so a level with few
+    // buckets and many contributions (a small table: a coarse level stored
+    // densely or sized to its share) puts all of them on a few CUs while the
+    // rest idle.  A bucket expected to hold more than a CU's share of all
+    // records (N V per level, before merging; none for privatised levels) is
+    // split over ks workgroups, each summing a contiguous part of its records
+    // into its own partial slice; a second pass adds the partials in order.
+    {
+        double total = 0.0;
+        for (int q = 0; q < L; ++q) total += q < b.P ? 0.0 : per_level;
+        const double per_cu = total / 256.0;
+        for (int q = 0; q < L; ++q) {
+            const double e = q < b.P ? 0.0 : per_level / (double)b.nb[q];
+            int k = 1;
+            if (e > 65536.0 && e > per_cu) {
+                const double want = e / per_cu;
+                k = want > 256.0 ? 256 : (int)want + 1;
+            }
+            b.ks[q] = k;
+        }
+    }
+    size_t split_floats = 0;  // the largest group's partial slices
+    for (int g = 0; g < b.groups; ++g) {
+        size_t n = 0;
+        for (int q = b.gl[g]; q < b.gl[g + 1]; ++q)
+            if (b.ks[q] > 1) n += (size_t)b.nb[q] * b.ks[q] * ((size_t)F << s);
+        if (n > split_floats) split_floats = n;
+    }
     size_t off = 0;
     b.off_counts = off;
     off = bin_align(off + (size_t)b.W * b.Bmax * 4);
@@ -234,6 +270,8 @@ inline BinLayout bin_layout(int D, int F, int64_t N, bool simplex, const LevelAr
     off = bin_align(off + (size_t)b.W * b.Dtot * F * 4);
     b.off_gdense = off;
     off = bin_align(off + (size_t)b.Dtot * F * 4);
+    b.off_split = off;
+    off = bin_align(off + split_floats * 4);
     b.off_recs = off;
     off = bin_align(off + (size_t)N * b.lmax * b.V * b.rec_bytes);
     b.total_bytes = off;
@@ -261,11 +299,31 @@ inline BinPlan bin_plan(const BinLayout& lay, int g, char* ws) {
     }
     p.boff[p.l1] = acc;
     p.B = acc;
+    int vacc = 0, sacc = 0;
+    int64_t sl = 0;
+    for (int l = 0; l < 32; ++l) p.ks[l] = lay.ks[l];
+    for (int l = 0; l < 33; ++l) p.voff[l] = p.sboff[l] = 0, p.soff[l] = 0;
+    for (int l = p.l0; l < p.l1; ++l) {
+        p.voff[l] = vacc;
+        p.sboff[l] = sacc;
+        p.soff[l] = sl;
+        vacc += lay.nb[l] * lay.ks[l];
+        if (lay.ks[l] > 1) {
+            sacc += lay.nb[l];
+            sl += (int64_t)lay.nb[l] * lay.ks[l];
+        }
+    }
+    p.voff[p.l1] = vacc;
+    p.sboff[p.l1] = sacc;
+    p.soff[p.l1] = sl;
+    p.VB = vacc;
+    p.nsplit = sacc;
     p.counts = (uint32_t*)(ws + lay.off_counts);
     p.base = (uint32_t*)(ws + lay.off_base);
     p.recs = ws + lay.off_recs;
     p.partial = (float*)(ws + lay.off_partial);
     p.gdense = (float*)(ws + lay.off_gdense);
+    p.split = (float*)(ws + lay.off_split);
     return p;
 }
 

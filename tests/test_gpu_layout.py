@@ -184,3 +184,86 @@ def test_layout_image_workload_full_size(cell):
     for l in range(16):
         r0, r1 = lay["offsets"][l], lay["offsets"][l + 1]
         assert np.all(np.abs(a[r0:r1] - b[r0:r1]) <= 2.0 ** -24 * (len(pts) * 3 + 8) * scale[l] + 1e-30), l
+
+
+def _split_factors(enc, N):
+    """The library's split rule for the binned accumulation: a bucket
+    expected to hold more than 65536 records and more than one CU's share
+    (of 256) of all records is shared by up to 256 workgroups."""
+    lay = spx.spx_table_layout(enc)
+    F, n, L = enc.n_feat, enc.n_dims, enc.n_levels
+    V = enc.n_vertices
+    s = min(15 - {1: 0, 2: 1, 4: 2, 8: 3}[F], enc.log2_T)
+    nb = [-(-r // (1 << s)) for r in lay["rows"]]
+    P, tot = 0, 0
+    for e in lay["box_extent"]:
+        if tot + e ** n > (96 * 1024) // (4 * F):
+            break
+        tot += e ** n
+        P += 1
+    per_level = float(N * V)
+    per_cu = sum(0.0 if q < P else per_level for q in range(L)) / 256.0
+    ks = []
+    for q in range(L):
+        e = 0.0 if q < P else per_level / nb[q]
+        ks.append(min(256, int(e / per_cu) + 1) if e > 65536 and e > per_cu else 1)
+    return ks
+
+
+SPLIT_CASES = [
+    # levels too large to privatise whose tables hold one or two buckets
+    (2, [70, 90, 300], 16, spx.SPX_LAYOUT_SIZED, spx.SPX_SIMPLEX),
+    (2, [70, 90], 14, spx.SPX_LAYOUT_HASHED, spx.SPX_SIMPLEX),
+    (3, [24, 30, 60], 16, spx.SPX_LAYOUT_SIZED, spx.SPX_GRID),
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=["sized-n2", "hashed-n2", "sized-n3-grid"])
+def test_split_buckets_bwd_and_adam(case):
+    """Buckets shared by several accumulation workgroups (a few buckets per
+    level, many contributions): the binned adjoint against the oracle's per
+    row bound, and the adjoint fused with Adam against the oracle's adjoint
+    followed by its Adam step, binary16 copy bit-exact."""
+    n, res, log2_T, layout, cell = case
+    N = 1 << 17
+    g = spx.Encoding(n, res, log2_T, 2, table_dtype=spx.SPX_F16, cell=cell, layout=layout)
+    o = oracle.Encoding(n, res, log2_T, 2, table_dtype=oracle.F16, cell=cell,
+                        layout=oracle.SIZED if layout == spx.SPX_LAYOUT_SIZED else oracle.HASHED)
+    assert max(_split_factors(g, N)) > 1
+    pts = inputs.uniform_points(N, n, 100 + n)
+    d = inputs.gradients(N, len(res) * 2, 101 + n) * 1e-3
+    got = _gpu_bwd(g, pts, d, binned=True)
+    ref, mag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
+    tol = (cnt + n + 2) * 2.0 ** -24 * mag + 1e-30
+    err = np.abs(got - ref)
+    assert (err <= tol).all(), f"worst {err.max()} ; {int((err > tol).sum())} rows out of tolerance"
+    # fused with Adam (the bounds of test_layout_bwd_adam_fused)
+    shape = g.table_shape
+    rng = np.random.default_rng(102)
+    p0 = (rng.normal(size=shape) * 1e-2).astype(np.float32)
+    m0 = (rng.normal(size=shape) * 1e-3).astype(np.float32)
+    v0 = (rng.random(shape) * 1e-5 + 1e-7).astype(np.float32)
+    f32 = lambda x: float(np.float32(x))
+    lr, b1, b2, eps, step = f32(1e-2), f32(0.9), f32(0.99), f32(1e-15), 3
+    tp, tm, tv = (torch.from_numpy(a.copy()).to(DEV) for a in (p0, m0, v0))
+    th = torch.empty(shape, dtype=torch.float16, device=DEV)
+    ws = torch.empty(spx.spx_encode_bwd_workspace(g, N), dtype=torch.uint8, device=DEV)
+    spx.spx_encode_bwd_adam(g, torch.from_numpy(pts).to(DEV), torch.from_numpy(d).to(DEV), tp, tm, tv, th,
+                            lr=lr, beta1=b1, beta2=b2, eps=eps, step=step, workspace=ws)
+    torch.cuda.synchronize()
+    p, m, v, _ = oracle.adam_step(p0.ravel(), ref.ravel().astype(np.float32), m0.ravel(), v0.ravel(),
+                                  lr, b1, b2, eps, step)
+    gp, gm, gv = (t.cpu().numpy().ravel().astype(np.float64) for t in (tp, tm, tv))
+    u = 2.0 ** -24
+    G, TG = np.abs(ref.ravel()), tol.ravel() + u * np.abs(ref.ravel())
+    tol_m = 3 * u * (b1 * np.abs(m0.ravel()) + (1 - b1) * G) + (1 - b1) * TG
+    tol_v = 4 * u * (b2 * v0.ravel() + (1 - b2) * G ** 2) + (1 - b2) * (2 * G + TG) * TG
+    bc1, bc2 = 1 - b1 ** step, 1 - b2 ** step
+    sv = np.sqrt(np.maximum(v.astype(np.float64) - tol_v, 0) / bc2) + eps
+    upd = np.abs(p0.ravel().astype(np.float64) - p)
+    tol_p = (2 * u * np.abs(p) + 10 * u * upd + lr * (tol_m / bc1) / sv + upd * 0.5 * (tol_v / bc2) / (sv * sv))
+    for name, gotv, refv, tolv in [("m", gm, m, tol_m), ("v", gv, v, tol_v), ("p", gp, p, tol_p)]:
+        e = np.abs(gotv - refv)
+        assert (e <= tolv).all(), f"{name}: worst err/tol {np.max(e / tolv):.3f}"
+    np.testing.assert_array_equal(th.cpu().numpy().view(np.uint16).ravel(),
+                                  oracle.cast_f32_f16(gp.astype(np.float32)))
