@@ -236,15 +236,29 @@ __global__ __launch_bounds__(kBinBlock) void bin_scatter_kernel(int64_t N, const
 // The records and their positions are the same as the direct kernel's, up to
 // the order within a bucket (which the sums do not depend on beyond
 // rounding).
+//
+// Two shapes, chosen per call.  Levels of many buckets (the image
+// workload's 256 per level) need long rounds for their per-bucket runs to be
+// long: 12 contributions per thread per round and eight levels of output
+// gradient held per point, one workgroup per CU (154 registers).  Levels of
+// few buckets (at most kStageFewBuckets: the volume workload's 32) have long
+// runs anyway; there 10 contributions per thread and four levels of
+// gradient fit two workgroups per CU (at most 128 registers), which hides
+// more latency where cells have four or more vertices (volume step 2.22 ->
+// 2.05 ms; with three vertices it was slower: image workload 1.65 -> 1.78
+// ms, the n = 2 sweep's adjoint by 5 %).  The count pass takes the same
+// shape, as it must see the same rounds.
 constexpr int kStageBlock = 512;  // threads of the staged scatter (longer runs than kStageBlock)
-constexpr int kStageSlots = 12;  // contributions staged per thread per round
-constexpr int kStageGL = 8;      // levels of output gradient held per point
-// LDS budget of the staged kernel (one workgroup per CU); configurations
-// that need more use the direct kernel.
+constexpr int kStageFewBuckets = 64;
+__host__ __device__ constexpr int stage_slots(bool few) { return few ? 10 : 12; }  // contributions per thread per round
+__host__ __device__ constexpr int stage_gl(bool few) { return few ? 4 : 8; }       // levels of output gradient held per point
+__host__ __device__ constexpr int stage_waves(bool few) { return few ? 4 : 1; }    // minimum waves per SIMD
+// LDS budget of the staged kernel; configurations that need more use the
+// direct kernel.
 constexpr size_t kStageLdsMax = 150 * 1024;
 
-template <int V>
-constexpr int stage_ppt() { return V > kStageSlots ? 0 : kStageSlots / V; }
+template <int V, bool FEW>
+constexpr int stage_ppt() { return V > stage_slots(FEW) ? 0 : stage_slots(FEW) / V; }
 
 // LDS layout of the staged scatter (in 32-bit words): cursors [B], local
 // counts/offsets [bmax + 1] (bmax: the most buckets of one level), staged
@@ -253,9 +267,9 @@ struct StageLds {
     size_t cursor, loff, key, val, words;
 };
 __host__ __device__ inline size_t stage_round4(size_t w) { return (w + 3) & ~(size_t)3; }
-template <int V, int F>
+template <int V, int F, bool FEW>
 __host__ __device__ inline StageLds stage_lds(int B, int bpl) {
-    constexpr size_t CAP = (size_t)kStageBlock * stage_ppt<V>() * V;
+    constexpr size_t CAP = (size_t)kStageBlock * stage_ppt<V, FEW>() * V;
     StageLds s;
     s.cursor = 0;
     s.loff = stage_round4((size_t)B);
@@ -286,11 +300,11 @@ __device__ __forceinline__ void merge_run_wave(uint32_t& key, float (&v)[F]) {
 
 // Count pass for the staged scatter: the same rounds, lanes and merged runs,
 // so each workgroup reserves exactly the records it will write per bucket.
-template <class Tag, int D>
+template <class Tag, int D, bool FEW>
 __global__ __launch_bounds__(kStageBlock) void bin_count_staged_kernel(int64_t N, const float* __restrict__ pts,
                                                                       LevelArgs lv, BinPlan plan) {
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
-    constexpr int PPT = stage_ppt<V>();
+    constexpr int PPT = stage_ppt<V, FEW>();
     extern __shared__ uint32_t hist[];
     const int tid = threadIdx.x;
     for (int b = tid; b < plan.B; b += kStageBlock) hist[b] = 0;
@@ -339,16 +353,16 @@ __global__ __launch_bounds__(kStageBlock) void bin_count_staged_kernel(int64_t N
     for (int b = tid; b < plan.B; b += kStageBlock) row[b] = hist[b];
 }
 
-template <class Tag, int D, int F, typename GT>
-__global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t N, const float* __restrict__ pts,
-                                                                       const GT* __restrict__ d_out, LevelArgs lv,
-                                                                       BinPlan plan) {
+template <class Tag, int D, int F, typename GT, bool FEW>
+__global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_staged_kernel(
+    int64_t N, const float* __restrict__ pts, const GT* __restrict__ d_out, LevelArgs lv, BinPlan plan) {
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
-    constexpr int PPT = stage_ppt<V>();
+    constexpr int PPT = stage_ppt<V, FEW>();
+    constexpr int GL = stage_gl(FEW);
     constexpr uint32_t kNone = kNoKey;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t wave_sum[kStageBlock / 64];
-    const StageLds lay = stage_lds<V, F>(plan.B, plan.bmax);
+    const StageLds lay = stage_lds<V, F, FEW>(plan.B, plan.bmax);
     uint32_t* cursor = lds + lay.cursor;
     uint32_t* loff = lds + lay.loff;
     uint32_t* skey = lds + lay.key;
@@ -370,20 +384,20 @@ __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t
             ok[j] = pt < hi;
             load_point<Tag, D>(pts, ok[j] ? pt : lo, lv.Fn, y[j]);
         }
-        // The points' output gradients are read kStageGL levels at a time
+        // The points' output gradients are read GL levels at a time
         // into registers: between two levels of the same point a whole round
         // passes, long enough for its row to leave L2, so reading one level
         // per visit would fetch each row's lines once per level.
-        float gch[PPT][kStageGL][F];
+        float gch[PPT][GL][F];
         for (int l = plan.l0; l < plan.l1; ++l) {
-            const int li = (l - plan.l0) % kStageGL;
+            const int li = (l - plan.l0) % GL;
             if (li == 0) {
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
                     const int64_t pt = r0 + tid + (int64_t)j * kStageBlock;
                     const GT* __restrict__ grow = d_out + (ok[j] ? pt : lo) * (int64_t)(lv.L * F);
 #pragma unroll
-                    for (int q = 0; q < kStageGL; ++q)
+                    for (int q = 0; q < GL; ++q)
                         if (l + q < plan.l1) RowIO<GT, F>::load(grow + (l + q) * F, gch[j][q]);
                 }
             }
@@ -403,7 +417,7 @@ __global__ __launch_bounds__(kStageBlock) void bin_scatter_staged_kernel(int64_t
 #pragma unroll
                 for (int f = 0; f < F; ++f) g[f] = gch[j][0][f];
 #pragma unroll
-                for (int q = 1; q < kStageGL; ++q)
+                for (int q = 1; q < GL; ++q)
                     if (li == q)
 #pragma unroll
                         for (int f = 0; f < F; ++f) g[f] = gch[j][q][f];
@@ -572,17 +586,26 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     // vertex and feature (however many records carry it)
     const double payload = N * (p.l1 - p.l0) * V * F * 4.0;
     // The staged scatter (when its LDS fits) merges runs of one slot across
-    // lanes, and its count pass counts the merged records the same way.
+    // lanes, and its count pass counts the merged records the same way, in
+    // the same shape (few buckets per level or many).
+    const bool few = p.bmax <= kStageFewBuckets && V >= 4;
     bool staged = false;
     size_t staged_lds = 0;
-    if constexpr (stage_ppt<V>() >= 1) {
-        staged_lds = stage_lds<V, F>(p.B, p.bmax).words * sizeof(uint32_t);
+    if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
+        staged_lds = (few ? stage_lds<V, F, true>(p.B, p.bmax) : stage_lds<V, F, false>(p.B, p.bmax)).words *
+                     sizeof(uint32_t);
         staged = staged_lds <= kStageLdsMax;
     }
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     if (staged) {
-        if constexpr (stage_ppt<V>() >= 1)
-            bin_count_staged_kernel<Tag, D><<<p.W, kStageBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
+        if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
+            if (few)
+                bin_count_staged_kernel<Tag, D, true><<<p.W, kStageBlock, p.B * sizeof(uint32_t), c.stream>>>(
+                    c.N, c.pts, c.lv, p);
+            else
+                bin_count_staged_kernel<Tag, D, false><<<p.W, kStageBlock, p.B * sizeof(uint32_t), c.stream>>>(
+                    c.N, c.pts, c.lv, p);
+        }
     } else {
         bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
     }
@@ -622,9 +645,14 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     }
     trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + payload);
     if (staged) {
-        if constexpr (stage_ppt<V>() >= 1)
-            bin_scatter_staged_kernel<Tag, D, F, GT><<<p.W, kStageBlock, staged_lds, c.stream>>>(c.N, c.pts, d_out, c.lv,
-                                                                                               p);
+        if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
+            if (few)
+                bin_scatter_staged_kernel<Tag, D, F, GT, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p);
+            else
+                bin_scatter_staged_kernel<Tag, D, F, GT, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p);
+        }
     } else
         bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv,
                                                                                                 p);
