@@ -726,7 +726,8 @@ def layout_accuracy(steps=2000):
     """Sec. 5.2's table sizing: the image and volume workloads trained with
     every level hashed into T rows (the paper's configurations) and with the
     sized layout (dense coarse levels, hashed levels sized by the simplex's
-    used share); held-out PSNR, table memory and step time."""
+    used share), beside the grid with hashed tables on the same batches;
+    held-out PSNR, table memory and step time."""
     from paper_2311_15439_amd import inputs, spx
     out = {}
     for w, d_out in ((inputs.IMAGE_2D, 3), (inputs.VOLUME_3D, 4)):
@@ -734,10 +735,13 @@ def layout_accuracy(steps=2000):
         weights = inputs.mlp_weights(w.n_levels * w.n_feat, 64, d_out, 9)
         out[w.name] = equal_accuracy(w, host_tables, weights, d_out, steps=steps, n_train=4,
                                      variants=(("hashed", spx.SPX_SIMPLEX, False, spx.SPX_LAYOUT_HASHED),
-                                               ("sized", spx.SPX_SIMPLEX, False, spx.SPX_LAYOUT_SIZED)))
+                                               ("sized", spx.SPX_SIMPLEX, False, spx.SPX_LAYOUT_SIZED),
+                                               ("grid", spx.SPX_GRID, False, spx.SPX_LAYOUT_HASHED)))
         r = out[w.name]
         r["sized_memory_fraction"] = r["sized"]["table_rows"] / r["hashed"]["table_rows"]
         r["sized_minus_hashed_db"] = r["sized"]["psnr_db"] - r["hashed"]["psnr_db"]
+        r["sized_minus_grid_db"] = r["sized"]["psnr_db"] - r["grid"]["psnr_db"]
+        r["sized_speedup_vs_grid"] = r["grid"]["ms_per_step"] / r["sized"]["ms_per_step"]
     return out
 
 
@@ -1237,7 +1241,9 @@ def summary_lines(d):
                    f"{a['simplex']['ms_per_step']:.3f} / {a['grid']['ms_per_step']:.3f} ms (simplex / grid)")
     for name, a in (d.get("layout_accuracy") or {}).items():
         out.append(f"# table layout {name}: sized tables {a['sized_memory_fraction']:.3f} of the hashed rows, PSNR "
-                   f"{a['sized']['psnr_db']:.2f} vs {a['hashed']['psnr_db']:.2f} dB")
+                   f"{a['sized']['psnr_db']:.2f} vs {a['hashed']['psnr_db']:.2f} dB (grid {a['grid']['psnr_db']:.2f}); "
+                   f"step {a['sized']['ms_per_step']:.3f} / {a['hashed']['ms_per_step']:.3f} / "
+                   f"{a['grid']['ms_per_step']:.3f} ms (sized / hashed / grid)")
     sv = d.get("serving")
     if sv:
         loads = ", ".join(f"{l['load']:.0%}: p50 {l['p50_ms']:.2f} p99 {l['p99_ms']:.2f} ms" for l in sv["loads"])
@@ -1321,10 +1327,13 @@ def headline(d, value, steps, warmup, detail_path):
                                                          _r(a["simplex_speedup"], 3)]
     lay = d.get("layout_accuracy")
     if lay:
-        line["table_layout"] = {"cols": ["sized_memory_fraction", "sized_minus_hashed_db"]}
+        line["table_layout"] = {"cols": ["sized_memory_fraction", "sized_minus_hashed_db", "sized_minus_grid_db",
+                                         "sized_speedup_vs_grid"]}
         for name, a in lay.items():
             line["table_layout"][name.split(" ")[0]] = [_r(a["sized_memory_fraction"], 3),
-                                                        _r(a["sized_minus_hashed_db"], 3)]
+                                                        _r(a["sized_minus_hashed_db"], 3),
+                                                        _r(a.get("sized_minus_grid_db"), 3),
+                                                        _r(a.get("sized_speedup_vs_grid"), 3)]
     sv = d.get("serving")
     if sv:
         line["serving"] = {"saturation_points_per_s": _r(sv["saturation_points_per_s"]),

@@ -124,8 +124,11 @@ def _fake_detail():
                                                          grid={"psnr_db": 30.5, "ms_per_step": 4.0},
                                                          simplex_speedup=4.0)
                         for n in range(3, 7)},
-        "layout_accuracy": {w.name: {"hashed": {"psnr_db": 22.9}, "sized": {"psnr_db": 22.8},
-                                     "sized_memory_fraction": 0.43, "sized_minus_hashed_db": -0.1}
+        "layout_accuracy": {w.name: {"hashed": {"psnr_db": 22.9, "ms_per_step": 1.6},
+                                     "sized": {"psnr_db": 22.8, "ms_per_step": 1.4},
+                                     "grid": {"psnr_db": 23.0, "ms_per_step": 1.8},
+                                     "sized_memory_fraction": 0.43, "sized_minus_hashed_db": -0.1,
+                                     "sized_minus_grid_db": -0.2, "sized_speedup_vs_grid": 1.29}
                             for w in (inputs.IMAGE_2D, inputs.VOLUME_3D)},
         "serving": {"saturation_points_per_s": 4.2e8,
                     "loads": [{"load": 0.5, "p50_ms": 1.4, "p99_ms": 5.2, "points_per_s": 2e8},
