@@ -178,7 +178,11 @@ spx_status spx_hash_primes(uint32_t* primes_out);
  *            size, at most 16 bytes).
  *   out      device [N][L*F] of out_dtype (SPX_F32 or SPX_F16), aligned to
  *            F * element size (at most 16 bytes).  Overwritten.
- * Deterministic: the same inputs give bit-identical outputs.
+ * Deterministic: the same inputs give bit-identical outputs.  From three
+ * dimensions and 2^18 points, when the levels' reachable rows exceed an
+ * XCD's 4 MiB L2 together but fit one by one, the launch is level-major:
+ * groups of consecutive levels up to 4 MiB, one group after the other over
+ * all points (the same outputs, faster).
  */
 spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, const void* tables,
                           void* out, int32_t out_dtype, hipStream_t stream);
@@ -494,7 +498,11 @@ spx_status spx_field_query_batched(const spx_field* fields, int32_t nfields, con
  * 1..16).  Per 16-point tile each lane encodes four levels of one point,
  * which are exactly its operand of the network's first matrix product, so
  * the features go from the gathers to the matrix cores in registers; they
- * are also stored (if feats is not NULL) for the network's backward.
+ * are also stored (if feats is not NULL) for the network's backward.  When
+ * feats is given and the level-major forward of spx_encode_fwd applies
+ * (3-D, at least 2^18 points, each group of levels fits an XCD's L2 while
+ * all levels together do not), the call runs spx_encode_fwd and
+ * spx_mlp_fwd instead, which is faster there; the results are the same.
  *   feats  device [N][32] binary16, 16-byte aligned, or NULL: identical to
  *          spx_encode_fwd with a binary16 output.
  *   out    device [N][d_out] binary32, 4-byte aligned: identical to

@@ -563,6 +563,15 @@ spx_status spx_encode_mlp_fwd(const spx_encoding* enc, const spx_mlp* mlp, int64
     if (N == 0) return SPX_OK;
     if (!out) return fail(SPX_EINVAL, "out is NULL");
     if (!aligned(out, 4) || (feats && !aligned(feats, 16))) return fail(SPX_EALIGN, "out 4-byte, feats 16-byte aligned");
+    // Where the level-major forward applies (each group of levels fits an
+    // XCD's L2, all levels together do not), it and the network forward as
+    // two kernels beat the fused kernel, which gathers from every level at
+    // once: the features make one round trip through memory, which needs
+    // the caller's feature buffer.  The same bits either way.
+    if (feats && spx::fwd_level_groups(level_args(enc), enc->n_dims, 4, N).n > 0) {
+        if ((st = spx_encode_fwd(enc, N, pts, tables, feats, SPX_F16, stream))) return st;
+        return spx_mlp_fwd(mlp, N, feats, W1, W2, W3, out, stream);
+    }
     return from_hip(spx::encode_mlp_fwd(f, N, pts, out, feats, stream), "spx_encode_mlp_fwd launch");
 }
 

@@ -213,7 +213,7 @@ def _split_factors(enc, N):
 SPLIT_CASES = [
     # levels too large to privatise whose tables hold one or two buckets
     (2, [70, 90, 300], 16, spx.SPX_LAYOUT_SIZED, spx.SPX_SIMPLEX),
-    (2, [70, 90], 14, spx.SPX_LAYOUT_HASHED, spx.SPX_SIMPLEX),
+    (2, [70, 130], 14, spx.SPX_LAYOUT_HASHED, spx.SPX_SIMPLEX),
     (3, [24, 30, 60], 16, spx.SPX_LAYOUT_SIZED, spx.SPX_GRID),
 ]
 
