@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 LINE_BYTES = 128  # cache line of gfx950's vector L1 and L2
 # one 64-byte HBM access per random gather: the theoretical random-gather rate
 HBM_RANDOM_GATHERS_PER_S = HBM_PEAK_GBS * 1e9 / 64.0
-DETAIL_DEFAULT = os.path.join("gpurun_out", "bench_detail.json")
+DETAIL_DEFAULT = os.path.join("results", "bench_detail.json")  # the full record beside the one-line summary
 
 
 def expected_unique(M, k):

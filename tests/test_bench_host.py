@@ -138,7 +138,7 @@ def _fake_detail():
 
 def test_headline_is_compact_json():
     d = _fake_detail()
-    line = bench.headline(d, (1 << 20) / 1.652e-3, 20, 5, "gpurun_out/bench_detail.json")
+    line = bench.headline(d, (1 << 20) / 1.652e-3, 20, 5, "results/bench_detail.json")
     text = json.dumps(line, separators=(",", ":"))
     assert len(text) < 4096, len(text)
     back = json.loads(text)
