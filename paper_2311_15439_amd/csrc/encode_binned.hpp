@@ -300,7 +300,7 @@ __device__ __forceinline__ void merge_run_wave(uint32_t& key, float (&v)[F]) {
 
 // Count pass for the staged scatter: the same rounds, lanes and merged runs,
 // so each workgroup reserves exactly the records it will write per bucket.
-template <class Tag, int D, bool FEW>
+template <class Tag, int D, bool FEW, bool DENSE>
 __global__ __launch_bounds__(kStageBlock) void bin_count_staged_kernel(int64_t N, const float* __restrict__ pts,
                                                                       LevelArgs lv, BinPlan plan) {
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kStageBlock) void bin_count_staged_kernel(int64_t N
 #pragma unroll
                 for (int k = 0; k < V; ++k) key[j][k] = kNoKey;
                 if (!ok[j]) continue;
-                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.rule(l),
+                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.template rule_if<DENSE>(l),
                                [&](const auto& h, const auto& w, int base, const auto& cell, const auto&) {
                     constexpr int K = sizeof(w) / sizeof(float);
                     int32_t e0, stride[D];
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kStageBlock) void bin_count_staged_kernel(int64_t N
     for (int b = tid; b < plan.B; b += kStageBlock) row[b] = hist[b];
 }
 
-template <class Tag, int D, int F, typename GT, bool FEW>
+template <class Tag, int D, int F, typename GT, bool FEW, bool DENSE>
 __global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_staged_kernel(
     int64_t N, const float* __restrict__ pts, const GT* __restrict__ d_out, LevelArgs lv, BinPlan plan) {
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_sta
                     if (li == q)
 #pragma unroll
                         for (int f = 0; f < F; ++f) g[f] = gch[j][q][f];
-                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.rule(l),
+                visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.template rule_if<DENSE>(l),
                                [&](const auto& h, const auto& w, int base, const auto& cell, const auto&) {
                     constexpr int K = sizeof(w) / sizeof(float);
                     int32_t e0, stride[D];
@@ -597,14 +597,20 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
         staged = staged_lds <= kStageLdsMax;
     }
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
+    // Without a densely stored level the staged kernels never compute dense
+    // rows (they are bound by vector instructions where runs are merged).
+    const bool dense = c.lv.dense != 0;
     if (staged) {
         if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
-            if (few)
-                bin_count_staged_kernel<Tag, D, true><<<p.W, kStageBlock, p.B * sizeof(uint32_t), c.stream>>>(
-                    c.N, c.pts, c.lv, p);
+            const size_t lds = p.B * sizeof(uint32_t);
+            if (few && dense)
+                bin_count_staged_kernel<Tag, D, true, true><<<p.W, kStageBlock, lds, c.stream>>>(c.N, c.pts, c.lv, p);
+            else if (few)
+                bin_count_staged_kernel<Tag, D, true, false><<<p.W, kStageBlock, lds, c.stream>>>(c.N, c.pts, c.lv, p);
+            else if (dense)
+                bin_count_staged_kernel<Tag, D, false, true><<<p.W, kStageBlock, lds, c.stream>>>(c.N, c.pts, c.lv, p);
             else
-                bin_count_staged_kernel<Tag, D, false><<<p.W, kStageBlock, p.B * sizeof(uint32_t), c.stream>>>(
-                    c.N, c.pts, c.lv, p);
+                bin_count_staged_kernel<Tag, D, false, false><<<p.W, kStageBlock, lds, c.stream>>>(c.N, c.pts, c.lv, p);
         }
     } else {
         bin_count_kernel<Tag, D><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, c.lv, p);
@@ -646,11 +652,17 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + payload);
     if (staged) {
         if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
-            if (few)
-                bin_scatter_staged_kernel<Tag, D, F, GT, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+            if (few && dense)
+                bin_scatter_staged_kernel<Tag, D, F, GT, true, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p);
+            else if (few)
+                bin_scatter_staged_kernel<Tag, D, F, GT, true, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p);
+            else if (dense)
+                bin_scatter_staged_kernel<Tag, D, F, GT, false, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
                     c.N, c.pts, d_out, c.lv, p);
             else
-                bin_scatter_staged_kernel<Tag, D, F, GT, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                bin_scatter_staged_kernel<Tag, D, F, GT, false, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
                     c.N, c.pts, d_out, c.lv, p);
         }
     } else

@@ -50,6 +50,13 @@ struct LevelArgs {
         const int32_t on = -(int32_t)((dense >> l) & 1u);
         return SlotRule{rows[l] - 1u, ext[l] & on};
     }
+    // The same, for kernels instantiated per call on whether any level is
+    // dense: without one, the dense rows are never computed.
+    template <bool DENSE>
+    __host__ __device__ SlotRule rule_if(int l) const {
+        if constexpr (DENSE) return rule(l);
+        return SlotRule{rows[l] - 1u, 0};
+    }
 };
 
 // Level groups of the level-major forward: group g holds levels

@@ -47,9 +47,13 @@ __device__ __forceinline__ float dpp_take(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
 }
 
+// Each step is skipped when no lane of the wave adds in it (runs shorter
+// than the step's reach, or not crossing the rows it joins): one scalar
+// test against several vector instructions per value.
 template <int OFF, int F>
 __device__ __forceinline__ void run_row_step(float (&v)[F], int lane, int start) {
     const bool add = (lane & 15) >= OFF && lane - OFF >= start;
+    if (__ballot(add) == 0) return;
 #pragma unroll
     for (int j = 0; j < F; ++j) {
         const float t = dpp_take<kDppRowShr + OFF, 0xf>(v[j]);
@@ -71,16 +75,20 @@ __device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[F]) {
     run_row_step<4>(v, lane, start);
     run_row_step<8>(v, lane, start);
     const bool add15 = (lane & 16) != 0 && start < (lane & ~15);
+    if (__ballot(add15) != 0) {
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
-        const float t = dpp_take<kDppRowBcast15, 0xa>(v[j]);
-        if (add15) v[j] += t;
+        for (int j = 0; j < F; ++j) {
+            const float t = dpp_take<kDppRowBcast15, 0xa>(v[j]);
+            if (add15) v[j] += t;
+        }
     }
     const bool add31 = lane >= 32 && start < 32;
+    if (__ballot(add31) != 0) {
 #pragma unroll
-    for (int j = 0; j < F; ++j) {
-        const float t = dpp_take<kDppRowBcast31, 0xc>(v[j]);
-        if (add31) v[j] += t;
+        for (int j = 0; j < F; ++j) {
+            const float t = dpp_take<kDppRowBcast31, 0xc>(v[j]);
+            if (add31) v[j] += t;
+        }
     }
 }
 
