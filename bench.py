@@ -102,7 +102,8 @@ def _traffic_path(workload):
 # kernels whose counters the traffic file holds, and the sources that define them
 TRAFFIC_KERNELS = {"bin_accum_adam": ("bin_accum_kernel", "true")}
 TRAFFIC_SOURCES = ["paper_2311_15439_amd/csrc/binned_accum.hpp", "paper_2311_15439_amd/csrc/spx_internal.h",
-                   "paper_2311_15439_amd/csrc/encode_kernels.hpp", "paper_2311_15439_amd/csrc/lookup.hpp"]
+                   "paper_2311_15439_amd/csrc/encode_kernels.hpp", "paper_2311_15439_amd/csrc/lookup.hpp",
+                   "paper_2311_15439_amd/csrc/wave_runs.hpp"]
 
 
 def _sources_digest():
