@@ -201,7 +201,11 @@ spx_status spx_encode_fwd(const spx_encoding* enc, int64_t N, const float* pts, 
  *              spx_encode_bwd_workspace(), 256-byte aligned: contributions
  *              are first binned by slot range and summed in LDS, and each
  *              slot of d_tables is then updated by exactly one workgroup
- *              (no global atomics; much faster for large batches).
+ *              (no global atomics; much faster for large batches).  A
+ *              bucket of slots that would hold more than one CU's share of
+ *              the contributions (a small table with many contributions) is
+ *              summed by several workgroups into partial sums that a second
+ *              pass adds in a fixed order.
  *              workspace_bytes is its size.  Its contents on entry are
  *              ignored and on return undefined.
  */
@@ -211,8 +215,9 @@ spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, 
 
 /*
  * Workspace bytes the binned adjoint needs for N points (written to
- * *bytes): about N * L * V records of 8 to 64 bytes plus per-bucket
- * counters.  SPX_EUNSUPPORTED if the configuration cannot be binned (use the
+ * *bytes): about N * L * V records of 8 to 64 bytes, per-bucket counters,
+ * the privatised coarse levels' per-workgroup sums and the split buckets'
+ * partial sums.  SPX_EUNSUPPORTED if the configuration cannot be binned (use the
  * atomic path, workspace NULL).
  */
 spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* bytes);
