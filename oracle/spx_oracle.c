@@ -43,10 +43,10 @@
 /* Constants.                                                               */
 /* ------------------------------------------------------------------------ */
 
-/* Skew factor of Eq. 2 (Sec. 2.2(a)): F_n = (sqrt(n+1) - 1) / n. */
+/* Skew factor of Eq. 2 (Sec. 3.2(a)): F_n = (sqrt(n+1) - 1) / n. */
 double orc_skew_factor(int n) { return (sqrt((double)n + 1.0) - 1.0) / (double)n; }
 
-/* Unskew factor of Eq. 3 (Sec. 2.2(d)): G_n = (1 - 1/sqrt(n+1)) / n. */
+/* Unskew factor of Eq. 3 (Sec. 3.2(d)): G_n = (1 - 1/sqrt(n+1)) / n. */
 double orc_unskew_factor(int n) { return (1.0 - 1.0 / sqrt((double)n + 1.0)) / (double)n; }
 
 /* Adjustment scale of Sec. 5.1: S_n = sqrt(n+1), the image of the unit
@@ -360,7 +360,7 @@ static int simplex_lookup(int n, const float* y, float sigma, int32_t verts[][OR
 }
 
 /*
- * 2^n-corner grid lookup (the baseline of Sec. 2.1 / Alg. 1): p = N_l * x,
+ * 2^n-corner grid lookup (the baseline of Sec. 3.1 / Alg. 1): p = N_l * x,
  * corners c + b for b in {0,1}^n enumerated in binary order (bit i is axis
  * i), n-linear weights prod_i (b_i ? f_i : 1 - f_i).
  */

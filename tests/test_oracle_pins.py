@@ -36,12 +36,12 @@ def test_closed_form_constants():
         one = np.ones(n)
         skew = np.eye(n) + F * np.ones((n, n))     # Eq. 2 as a matrix (off-diagonal F_n)
         unskew = np.eye(n) - G * np.ones((n, n))   # Eq. 3
-        # the skew maps the far corner 1 to sqrt(n+1) * 1 (Sec. 2.2(a), Sec. 5.1)
+        # the skew maps the far corner 1 to sqrt(n+1) * 1 (Sec. 3.2(a), Sec. 5.1)
         np.testing.assert_allclose(skew @ one, math.sqrt(n + 1) * one, rtol=1e-15)
         np.testing.assert_allclose(S, math.sqrt(n + 1), rtol=0)
         # unskew undoes skew
         np.testing.assert_allclose(unskew @ skew, np.eye(n), atol=1e-15)
-        # distance 0 -> 1 equals distance 0 -> e_1 after the skew (Sec. 2.2(a))
+        # distance 0 -> 1 equals distance 0 -> e_1 after the skew (Sec. 3.2(a))
         assert np.linalg.norm(unskew @ one) == pytest.approx(np.linalg.norm(unskew @ np.eye(n)[0]), rel=1e-14)
 
 
