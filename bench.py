@@ -944,9 +944,10 @@ def cpu_baseline(w, host_tables, weights, batch, S=1 << 16):
             "cpu_model": model, "host_cores": ncpu}
 
 
-def serving_bench(n_fields=8, n_requests=2000, warm=200, loads=(0.5, 0.8), train_steps=30):
+def serving_bench(n_fields=8, n_requests=2000, warm=200, loads=(0.5, 0.8), train_steps=2000):
     """Serving: resident 3-D fields (n=3, L=16, T=2^19, F=2 binary16, MLP
-    32-64-64-4), each briefly trained on its own synthetic density; requests
+    32-64-64-4), each trained for train_steps Adam steps on its own
+    synthetic density (2^16 points per step); requests
     of log-uniform size 2^8..2^20 points on a uniformly chosen field.  First
     the saturation rate (requests submitted back to back), then Poisson
     arrivals at fractions of it; latency is submit -> results in host
@@ -963,6 +964,7 @@ def serving_bench(n_fields=8, n_requests=2000, warm=200, loads=(0.5, 0.8), train
     train_pts = inputs.uniform_points(1 << 16, 3, 99)
     tp = torch.from_numpy(train_pts).cuda()
     for f in range(n_fields):
+        print(f"# serving: training field {f} ({train_steps} steps)", file=sys.stderr, flush=True)
         enc = SimplexEncoding(3, w.n_levels, w.log2_T, 2, n_min=w.n_min, growth=w.growth, seed=20 + f)
         net = TinyMLP(32, 4, seed=40 + f)
         field = NeuralField(enc, net)
@@ -988,7 +990,7 @@ def serving_bench(n_fields=8, n_requests=2000, warm=200, loads=(0.5, 0.8), train
         return [(int(f), pool[s:s + m]) for f, s, m in zip(fields, starts, sizes)]
 
     be = GpuBackend(descs)
-    srv = Server(be, [3] * n_fields, [4] * n_fields, arena_bytes=512 << 20, chunk_points=1 << 18,
+    srv = Server(be, [3] * n_fields, [4] * n_fields, arena_bytes=1 << 30, chunk_points=1 << 18,
                  batch_points=1 << 21).start()
     try:
         for f, p in make(warm):
