@@ -63,6 +63,8 @@ __device__ __forceinline__ void lds_add_row(float* row, const float (&v)[F]) {
 }
 
 constexpr int kAccBlock = 1024;  // one workgroup per CU (128 KiB accumulator)
+// records loaded per thread before their LDS adds (two were no faster and
+// spilled registers beside the preloaded state)
 constexpr int kAccUnroll = 1;
 
 // Adam update of four parameters with their summed gradients (the same
@@ -196,8 +198,8 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
         r1 = r0 + (uint32_t)(n * (uint64_t)(part + 1) / (uint64_t)K);
         r0 = r0 + (uint32_t)(n * (uint64_t)part / (uint64_t)K);
     }
-    // several records in flight per thread before their LDS adds; the loop
-    // bounds are uniform over the workgroup (lanes past the end idle)
+    // kAccUnroll records per thread in flight before their LDS adds; the
+    // loop bounds are uniform over the workgroup (lanes past the end idle)
     for (uint32_t rb = r0; rb < r1; rb += kAccUnroll * kAccBlock) {
         BinRec<F> rec[kAccUnroll];
         bool ok[kAccUnroll];
