@@ -519,6 +519,49 @@ spx_status spx_encode_mlp_fwd(const spx_encoding* enc, const spx_mlp* mlp, int64
                               const void* tables, const uint16_t* W1, const uint16_t* W2, const uint16_t* W3,
                               uint16_t* feats, float* out, hipStream_t stream);
 
+/*
+ * Network backward and encoding adjoint with the tables' Adam step, fused
+ * (Sec. 5 steps (d)-(e) backward): the result of spx_mlp_bwd (with d_x)
+ * followed by spx_encode_bwd_adam of that d_x, without the input gradient
+ * d_x ever being stored.  The adjoint's scatter computes each point's
+ * input gradient itself on the matrix cores, from the stored features and
+ * the network's output gradient, with the same products as spx_mlp_bwd (the
+ * same bits), and emits its records from registers; only the units of the
+ * privatised coarse levels (whose dense per-workgroup sums run beside the
+ * scatter) are written to the workspace by the network backward.
+ * Covered: the network's input is the encoding (d_in = n_levels * n_feat =
+ * 32), n_feat = 2, n_dims 1..3, an adjoint that runs in one level group
+ * (at most 16384 buckets and 2 GiB of records) with a staged scatter whose
+ * LDS, with the network's weights, fits the CU; otherwise SPX_EUNSUPPORTED,
+ * before anything is launched.
+ *   x            device [N][32] binary16 features (the forward's), 16-byte aligned.
+ *   W1, W2, W3   device binary16 weights as spx_mlp_fwd, 16-byte aligned.
+ *   d_y          device [N][d_out] binary32 output gradient, 4-byte aligned.
+ *   dW1..dW3     as spx_mlp_bwd: OVERWRITTEN with the weight gradients
+ *                (deterministic, bit-identical to spx_mlp_bwd).
+ *   param, m, v, param_f16, lr, beta1, beta2, eps, step
+ *                as spx_encode_bwd_adam (every table entry takes its step).
+ *   workspace    device, at least spx_encode_mlp_bwd_workspace() bytes,
+ *                256-byte aligned; contents on entry ignored, on return
+ *                undefined.
+ * The tables' summation order varies from run to run, as in
+ * spx_encode_bwd_adam.
+ */
+spx_status spx_encode_mlp_bwd_adam(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, const float* pts,
+                                   const uint16_t* x, const uint16_t* W1, const uint16_t* W2, const uint16_t* W3,
+                                   const float* d_y, float* dW1, float* dW2, float* dW3, float* param, float* m,
+                                   float* v, uint16_t* param_f16, float lr, float beta1, float beta2, float eps,
+                                   int64_t step, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Workspace bytes spx_encode_mlp_bwd_adam needs for N points (written to
+ * *bytes): the binned adjoint's workspace, the network backward's
+ * weight-gradient partials and N rows of the privatised levels' input
+ * gradient.  SPX_EUNSUPPORTED for configurations the fused path does not
+ * cover.
+ */
+spx_status spx_encode_mlp_bwd_workspace(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, size_t* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -409,6 +409,34 @@ spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, 
     return from_hip(run(enc, c), "spx_encode_bwd launch");
 }
 
+static spx_status check_adam(const float* param, const float* m, const float* v, const uint16_t* param_f16,
+                             float beta1, float beta2, float eps, int64_t step) {
+    if (step < 1) return fail(SPX_EINVAL, "step=%lld < 1", (long long)step);
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return fail(SPX_EINVAL, "beta1/beta2 must lie in [0,1) and eps >= 0");
+    if (!param || !m || !v) return fail(SPX_EINVAL, "param, m or v is NULL");
+    if (!aligned(param, 16) || !aligned(m, 16) || !aligned(v, 16) || (param_f16 && !aligned(param_f16, 8)))
+        return fail(SPX_EALIGN, "Adam state misaligned (param/m/v 16 bytes, param_f16 8 bytes)");
+    return SPX_OK;
+}
+
+static spx::AdamArgs adam_args(float* param, float* m, float* v, uint16_t* param_f16, float lr, float beta1,
+                               float beta2, float eps, int64_t step) {
+    spx::AdamArgs a;
+    memset(&a, 0, sizeof(a));
+    a.param = param;
+    a.m = m;
+    a.v = v;
+    a.param_f16 = param_f16;
+    a.lr = lr;
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.inv_bc1 = 1.0f / (float)(1.0 - pow((double)beta1, (double)step));
+    a.inv_bc2 = 1.0f / (float)(1.0 - pow((double)beta2, (double)step));
+    return a;
+}
+
 spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
                                int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
                                float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
@@ -417,12 +445,7 @@ spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* 
     if (st) return st;
     if ((st = check_points(N, pts))) return st;
     if (d_out_dtype != SPX_F32 && d_out_dtype != SPX_F16) return fail(SPX_EINVAL, "d_out_dtype=%d", d_out_dtype);
-    if (step < 1) return fail(SPX_EINVAL, "step=%lld < 1", (long long)step);
-    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
-        return fail(SPX_EINVAL, "beta1/beta2 must lie in [0,1) and eps >= 0");
-    if (!param || !m || !v) return fail(SPX_EINVAL, "param, m or v is NULL");
-    if (!aligned(param, 16) || !aligned(m, 16) || !aligned(v, 16) || (param_f16 && !aligned(param_f16, 8)))
-        return fail(SPX_EALIGN, "Adam state misaligned (param/m/v 16 bytes, param_f16 8 bytes)");
+    if ((st = check_adam(param, m, v, param_f16, beta1, beta2, eps, step))) return st;
     if (N > 0 && !d_out) return fail(SPX_EINVAL, "d_out is NULL");
     const int ge = d_out_dtype == SPX_F16 ? 2 : 4;
     if (d_out && !aligned(d_out, row_align(enc->n_feat, ge))) return fail(SPX_EALIGN, "d_out not row-aligned");
@@ -436,16 +459,7 @@ spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* 
     c.workspace = workspace;
     c.dout_f16 = d_out_dtype == SPX_F16;
     c.d_out = d_out;
-    c.adam.param = param;
-    c.adam.m = m;
-    c.adam.v = v;
-    c.adam.param_f16 = param_f16;
-    c.adam.lr = lr;
-    c.adam.b1 = beta1;
-    c.adam.b2 = beta2;
-    c.adam.eps = eps;
-    c.adam.inv_bc1 = 1.0f / (float)(1.0 - pow((double)beta1, (double)step));
-    c.adam.inv_bc2 = 1.0f / (float)(1.0 - pow((double)beta2, (double)step));
+    c.adam = adam_args(param, m, v, param_f16, lr, beta1, beta2, eps, step);
     return from_hip(run(enc, c), "spx_encode_bwd_adam launch");
 }
 
@@ -627,7 +641,7 @@ spx_status spx_mlp_bwd_workspace(const spx_mlp* mlp, int64_t N, size_t* bytes) {
 static spx_status mlp_bwd_checked(const spx_mlp* mlp, int64_t N, const uint16_t* x, const uint16_t* W1,
                                   const uint16_t* W2, const uint16_t* W3, const float* d_y, float* d_x, float* dW1,
                                   float* dW2, float* dW3, void* workspace, size_t workspace_bytes,
-                                  hipStream_t stream, const char* fn) {
+                                  hipStream_t stream, const char* fn, int dx_cols = 0, int dx_stride = 0) {
     spx_status st = check_mlp(mlp, N);
     if (st) return st;
     if (!W1 || !W2 || !W3 || !dW1 || !dW2 || !dW3) return fail(SPX_EINVAL, "NULL weight pointer");
@@ -664,6 +678,8 @@ static spx_status mlp_bwd_checked(const spx_mlp* mlp, int64_t N, const uint16_t*
     c.W3 = W3;
     c.d_y = d_y;
     c.d_x = d_x;
+    c.dx_cols = dx_cols;
+    c.dx_stride = dx_stride;
     c.dW1 = dW1;
     c.dW2 = dW2;
     c.dW3 = dW3;
@@ -694,6 +710,94 @@ spx_status spx_mlp_bwd_noalloc(const spx_mlp* mlp, int64_t N, const uint16_t* x,
                     scratch_bytes);
     return mlp_bwd_checked(mlp, N, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, scratch, scratch_bytes, stream,
                            "spx_mlp_bwd_noalloc launch");
+}
+
+// Workspace of the fused network backward and adjoint: the binned
+// adjoint's, then the network backward's weight-gradient partials, then the
+// privatised coarse levels' units of the input gradient (rows of
+// coarse_stride floats).
+struct NetWorkspace {
+    size_t mlp, coarse, total;
+    int coarse_cols, coarse_stride;
+};
+
+static NetWorkspace net_workspace(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, const spx::BinLayout& lay) {
+    NetWorkspace w;
+    w.coarse_cols = lay.P * enc->n_feat;
+    w.coarse_stride = (w.coarse_cols + 3) & ~3;
+    w.mlp = spx::bin_align(lay.total_bytes);
+    w.coarse = w.mlp + spx::bin_align(spx::mlp_bwd_workspace_bytes(mlp->d_in, mlp->hidden, mlp->d_out, N));
+    w.total = w.coarse + spx::bin_align((size_t)N * w.coarse_stride * sizeof(float));
+    return w;
+}
+
+// What the fused path covers, before any launch: the network's input is the
+// encoding (d_in = L * F), 2 features per level, 1 to 3 dimensions, and the
+// adjoint's staged scatter fits one level group and the CU's LDS.
+static spx_status net_covers(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, const spx::BinLayout& lay) {
+    if (mlp->d_in != enc->n_levels * enc->n_feat)
+        return fail(SPX_EINVAL, "d_in=%d is not n_levels * n_feat = %d", mlp->d_in, enc->n_levels * enc->n_feat);
+    if (enc->n_feat != 2 || enc->n_dims > 3)
+        return fail(SPX_EUNSUPPORTED, "the fused network backward covers n_feat = 2 and n_dims <= 3");
+    if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
+    spx::EncodeCall c = base_call(enc, N, nullptr, nullptr);
+    c.op = spx::EncodeOp::AdjointBinned;
+    c.net.check_only = 1;
+    const hipError_t he = run(enc, c);
+    if (he == hipErrorNotSupported)
+        return fail(SPX_EUNSUPPORTED, "the fused network backward needs one level group and a staged scatter "
+                                      "whose LDS (with the network's weights) fits the CU");
+    return from_hip(he, "fused network backward check");
+}
+
+spx_status spx_encode_mlp_bwd_workspace(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, size_t* bytes) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_mlp(mlp, N))) return st;
+    if (!bytes) return fail(SPX_EINVAL, "bytes is NULL");
+    const spx::BinLayout lay = layout_for(enc, N);
+    if ((st = net_covers(enc, mlp, N, lay))) return st;
+    *bytes = net_workspace(enc, mlp, N, lay).total;
+    return SPX_OK;
+}
+
+spx_status spx_encode_mlp_bwd_adam(const spx_encoding* enc, const spx_mlp* mlp, int64_t N, const float* pts,
+                                   const uint16_t* x, const uint16_t* W1, const uint16_t* W2, const uint16_t* W3,
+                                   const float* d_y, float* dW1, float* dW2, float* dW3, float* param, float* m,
+                                   float* v, uint16_t* param_f16, float lr, float beta1, float beta2, float eps,
+                                   int64_t step, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if ((st = check_mlp(mlp, N))) return st;
+    if ((st = check_adam(param, m, v, param_f16, beta1, beta2, eps, step))) return st;
+    const spx::BinLayout lay = layout_for(enc, N);
+    if ((st = net_covers(enc, mlp, N, lay))) return st;
+    const NetWorkspace w = net_workspace(enc, mlp, N, lay);
+    if (!workspace || workspace_bytes < w.total)
+        return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", w.total, workspace_bytes);
+    if (!aligned(workspace, 256)) return fail(SPX_EALIGN, "workspace not 256-byte aligned");
+    char* ws = (char*)workspace;
+    float* coarse = (float*)(ws + w.coarse);
+    // the network backward: weight gradients, and the input gradient's units
+    // of the privatised coarse levels (the scatter computes the rest itself)
+    st = mlp_bwd_checked(mlp, N, x, W1, W2, W3, d_y, w.coarse_cols > 0 ? coarse : nullptr, dW1, dW2, dW3,
+                         ws + w.mlp, w.coarse - w.mlp, stream, "spx_encode_mlp_bwd_adam network backward",
+                         w.coarse_cols, w.coarse_stride);
+    if (st) return st;
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::AdjointBinned;
+    c.workspace = workspace;
+    c.d_out = coarse;
+    c.net.x = reinterpret_cast<const _Float16*>(x);
+    c.net.W1 = reinterpret_cast<const _Float16*>(W1);
+    c.net.W2 = reinterpret_cast<const _Float16*>(W2);
+    c.net.W3 = reinterpret_cast<const _Float16*>(W3);
+    c.net.d_y = d_y;
+    c.net.d_out = mlp->d_out;
+    c.net.coarse_stride = w.coarse_stride;
+    c.adam = adam_args(param, m, v, param_f16, lr, beta1, beta2, eps, step);
+    return from_hip(run(enc, c), "spx_encode_mlp_bwd_adam launch");
 }
 
 }  // extern "C"

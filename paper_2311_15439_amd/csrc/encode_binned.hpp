@@ -35,8 +35,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "binned_accum.hpp"
 #include "encode_kernels.hpp"
+#include "mfma_mlp.hpp"
 
 namespace spx {
 
@@ -353,14 +356,44 @@ __global__ __launch_bounds__(kStageBlock) void bin_count_staged_kernel(int64_t N
     for (int b = tid; b < plan.B; b += kStageBlock) row[b] = hist[b];
 }
 
-template <class Tag, int D, int F, typename GT, bool FEW, bool DENSE>
-__global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_staged_kernel(
-    int64_t N, const float* __restrict__ pts, const GT* __restrict__ d_out, LevelArgs lv, BinPlan plan) {
+// The network's input gradient (NET below): all kNetUnits units of a
+// point, 16 levels of 2 features; transposed through LDS in rows of
+// kNetRow floats (16 units, padded against bank conflicts).
+constexpr int kNetUnits = 32;
+constexpr int kNetRow = 20;
+
+// LDS accesses of one wave to rows that other lanes of the same wave wrote:
+// a wave's LDS instructions execute in order, so only the compiler's
+// reordering has to be fenced.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// NET: the output gradient is not read from d_out but computed here, as the
+// input gradient of the network (Sec. 5 steps (d)-(e)) that maps the
+// encoding to the field: once per round, on the matrix cores, from the
+// stored binary16 features and the network's output gradient.  Each wave
+// takes its own points 16 at a time (lane (r, q) of a tile holds point r
+// and units 4q..4q+3 of each 16-unit half), and a per-wave transpose through
+// LDS hands every lane its point's 32 units, held in registers for the
+// round.  The products are the ones the separate network backward makes
+// (shared code), so the gradients are the same bits.  NET requires F = 2,
+// 16 levels and a single level group (l0 = 0, l1 = 16).
+template <class Tag, int D, int F, typename GT, bool FEW, bool DENSE, bool NET = false>
+__global__ __launch_bounds__(kStageBlock, NET ? 2 : stage_waves(FEW)) void bin_scatter_staged_kernel(
+    int64_t N, const float* __restrict__ pts, const GT* __restrict__ d_out, LevelArgs lv, BinPlan plan,
+    NetArgs net) {
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
     constexpr int PPT = stage_ppt<V, FEW>();
     constexpr int GL = stage_gl(FEW);
     constexpr uint32_t kNone = kNoKey;
-    extern __shared__ uint32_t lds[];
+    static_assert(!NET || (F == 2 && kNetUnits % (GL * F) == 0), "the network covers 16 levels of 2 features");
+    // the transpose rows of the 8 waves fit in the staging area (free between level passes)
+    static_assert(!NET || (kStageBlock / 64) * 64 * kNetRow <= kStageBlock * PPT * V * (1 + F),
+                  "transpose area exceeds the staging area");
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ uint32_t wave_sum[kStageBlock / 64];
     const StageLds lay = stage_lds<V, F, FEW>(plan.B, plan.bmax);
     uint32_t* cursor = lds + lay.cursor;
@@ -371,6 +404,13 @@ __global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_sta
 
     const uint32_t* row = plan.counts + (size_t)blockIdx.x * plan.B;
     for (int b = tid; b < plan.B; b += kStageBlock) cursor[b] = plan.base[b] + row[b];
+    // NET: the network's weight fragments, after the staging layout
+    const uint4* frag = reinterpret_cast<const uint4*>(lds + lay.words);
+    if constexpr (NET) {
+        stage_bwd_frags<kNetUnits>(reinterpret_cast<uint4*>(lds + lay.words), net.W1, net.W2, net.W3, net.d_out,
+                                   wave, kStageBlock / 64, lane);
+        __syncthreads();
+    }
     BinRec<F>* __restrict__ recs = reinterpret_cast<BinRec<F>*>(plan.recs);
     const uint32_t smask = (1u << plan.s_log2) - 1u;
     int64_t lo, hi;
@@ -384,14 +424,54 @@ __global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_sta
             ok[j] = pt < hi;
             load_point<Tag, D>(pts, ok[j] ? pt : lo, lv.Fn, y[j]);
         }
+        float gall[NET ? PPT : 1][NET ? kNetUnits : 1];
+        if constexpr (NET) {
+            // the staging area is free here: the previous round's last
+            // level pass ended with a barrier after its records left
+            float* tr = reinterpret_cast<float*>(lds + lay.key) + wave * (64 * kNetRow);
+            const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                // Tiles one after another (the scheduling barriers keep the
+                // four chains from being interleaved, which would hold four
+                // tiles' activations at once): units 0..15 go to the
+                // transpose rows at once, units 16..31 wait in registers.
+                f4 hi16[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t p = r0 + (int64_t)j * kStageBlock + wave * 64 + 16 * k + r;
+                    BwdTile<kNetUnits> tl;
+                    tl.run(frag, lane, net.x, net.d_y, net.d_out, p, p < hi);
+                    *reinterpret_cast<f4*>(tr + (16 * k + r) * kNetRow + 4 * q) = tl.dx(frag, lane, 0);
+                    hi16[k] = tl.dx(frag, lane, 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (h == 1) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            *reinterpret_cast<f4*>(tr + (16 * k + r) * kNetRow + 4 * q) = hi16[k];
+                    }
+                    wave_lds_sync();
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const f4 v = *reinterpret_cast<const f4*>(tr + lane * kNetRow + 4 * i);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) gall[j][16 * h + 4 * i + e] = v[e];
+                    }
+                    wave_lds_sync();
+                }
+            }
+        }
         // The points' output gradients are read GL levels at a time
         // into registers: between two levels of the same point a whole round
         // passes, long enough for its row to leave L2, so reading one level
         // per visit would fetch each row's lines once per level.
-        float gch[PPT][GL][F];
+        float gch[NET ? 1 : PPT][NET ? 1 : GL][F];
         for (int l = plan.l0; l < plan.l1; ++l) {
             const int li = (l - plan.l0) % GL;
-            if (li == 0) {
+            if (!NET && li == 0) {
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
                     const int64_t pt = r0 + tid + (int64_t)j * kStageBlock;
@@ -414,13 +494,25 @@ __global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_sta
                 for (int k = 0; k < V; ++k) key[j][k] = kNone;
                 if (!ok[j]) continue;
                 float g[F];
+                if constexpr (NET) {
+                    // level l's units, selected from the round's registers
+                    // (a copy per level group would double them)
 #pragma unroll
-                for (int f = 0; f < F; ++f) g[f] = gch[j][0][f];
+                    for (int f = 0; f < F; ++f) g[f] = gall[j][f];
 #pragma unroll
-                for (int q = 1; q < GL; ++q)
-                    if (li == q)
+                    for (int q = 1; q < kNetUnits / F; ++q)
+                        if (l == q)
 #pragma unroll
-                        for (int f = 0; f < F; ++f) g[f] = gch[j][q][f];
+                            for (int f = 0; f < F; ++f) g[f] = gall[j][q * F + f];
+                } else {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) g[f] = gch[j][0][f];
+#pragma unroll
+                    for (int q = 1; q < GL; ++q)
+                        if (li == q)
+#pragma unroll
+                            for (int f = 0; f < F; ++f) g[f] = gch[j][q][f];
+                }
                 visit_level_ex(Tag{}, y[j], lv.sigma[l], lv.template rule_if<DENSE>(l),
                                [&](const auto& h, const auto& w, int base, const auto& cell, const auto&) {
                     constexpr int K = sizeof(w) / sizeof(float);
@@ -504,8 +596,8 @@ __global__ __launch_bounds__(kStageBlock, stage_waves(FEW)) void bin_scatter_sta
 // chunk idle) because the wave-level adds need every lane.
 template <class Tag, int D, int F, typename GT>
 __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const float* __restrict__ pts,
-                                                               const GT* __restrict__ d_out, LevelArgs lv,
-                                                               BinPlan plan) {
+                                                               const GT* __restrict__ d_out, int64_t gstride,
+                                                               LevelArgs lv, BinPlan plan) {
     extern __shared__ __attribute__((aligned(16))) float dacc[];
     const int n = plan.Dtot * F;
     for (int i = threadIdx.x; i < n; i += kBinBlock) dacc[i] = 0.0f;
@@ -517,7 +609,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const 
         const int64_t pt = in ? p0 + threadIdx.x : lo;
         float y[D];
         load_point<Tag, D>(pts, pt, lv.Fn, y);
-        const GT* __restrict__ grow = d_out + pt * (int64_t)(lv.L * F);
+        const GT* __restrict__ grow = d_out + pt * gstride;
         for (int l = 0; l < plan.P; ++l) {
             float g[F];
             RowIO<GT, F>::load(grow + l * F, g);
@@ -575,10 +667,22 @@ static __global__ __launch_bounds__(kColBuckets * kColSegs) void bin_coarse_redu
     plan.gdense[i] = t;
 }
 
+// The fused network backward covers 16 levels of 2 features in 1 to 3
+// dimensions, one level group and a staged scatter whose LDS (with the
+// network's weight fragments) fits the CU.
+constexpr size_t kNetLdsMax = 160 * 1024 - 256;  // beside the kernel's static LDS
+
+template <int V, int F>
+inline size_t staged_lds_bytes(int B, int bmax, bool few) {
+    return (few ? stage_lds<V, F, true>(B, bmax) : stage_lds<V, F, false>(B, bmax)).words * sizeof(uint32_t);
+}
+
 template <class Tag, int D, int F, typename GT>
 hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
     const GT* d_out = (const GT*)c.d_out;
     constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+    constexpr bool kNetOk = F == 2 && D <= 3;
+    const bool net = c.net.x != nullptr;
     const double N = (double)c.N, gs = sizeof(GT), rec = sizeof(BinRec<F>);
     const double counts = (double)p.W * p.B * 4.0;
     (void)rec;
@@ -592,10 +696,11 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     bool staged = false;
     size_t staged_lds = 0;
     if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
-        staged_lds = (few ? stage_lds<V, F, true>(p.B, p.bmax) : stage_lds<V, F, false>(p.B, p.bmax)).words *
-                     sizeof(uint32_t);
+        staged_lds = staged_lds_bytes<V, F>(p.B, p.bmax, few);
         staged = staged_lds <= kStageLdsMax;
     }
+    if (net && (!kNetOk || !staged || staged_lds + BwdFrags<kNetUnits>::BYTES > kNetLdsMax))
+        return hipErrorNotSupported;  // checked by the caller before any launch
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     // Without a densely stored level the staged kernels never compute dense
     // rows (they are bound by vector instructions where runs are merged).
@@ -638,8 +743,10 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
             aux = nullptr;  // run the coarse levels in order on the caller's stream
         if (aux) cs = aux->s;
         const int n = p.Dtot * F;
+        const int64_t gstride = net ? c.net.coarse_stride : (int64_t)c.lv.L * F;
         trace_begin(cs, "bin_coarse", N * (4.0 * D + p.P * F * gs) + (double)p.W * n * 4.0);
-        bin_coarse_kernel<Tag, D, F, GT><<<p.W, kBinBlock, (size_t)n * sizeof(float), cs>>>(c.N, c.pts, d_out, c.lv, p);
+        bin_coarse_kernel<Tag, D, F, GT><<<p.W, kBinBlock, (size_t)n * sizeof(float), cs>>>(c.N, c.pts, d_out, gstride,
+                                                                                            c.lv, p);
         trace_end(cs);
         trace_begin(cs, "bin_coarse_reduce", ((double)p.W + 1.0) * n * 4.0);
         bin_coarse_reduce_kernel<<<(n + kColBuckets - 1) / kColBuckets, kColBuckets * kColSegs, 0, cs>>>(p, n);
@@ -649,25 +756,47 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
             if (e != hipSuccess) return e;
         }
     }
-    trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + payload);
-    if (staged) {
-        if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
+    if (net) {
+        // features and network output gradient in, instead of the output gradient
+        trace_begin(c.stream, "bin_scatter_net",
+                    N * (4.0 * D + 2.0 * kNetUnits + 4.0 * c.net.d_out) + counts + payload);
+        if constexpr (kNetOk && std::is_same<GT, float>::value && stage_ppt<V, false>() >= 1 &&
+                      stage_ppt<V, true>() >= 1) {
+            const size_t lds = staged_lds + BwdFrags<kNetUnits>::BYTES;
             if (few && dense)
-                bin_scatter_staged_kernel<Tag, D, F, GT, true, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
-                    c.N, c.pts, d_out, c.lv, p);
+                bin_scatter_staged_kernel<Tag, D, F, GT, true, true, true><<<p.W, kStageBlock, lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p, c.net);
             else if (few)
-                bin_scatter_staged_kernel<Tag, D, F, GT, true, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
-                    c.N, c.pts, d_out, c.lv, p);
+                bin_scatter_staged_kernel<Tag, D, F, GT, true, false, true><<<p.W, kStageBlock, lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p, c.net);
             else if (dense)
-                bin_scatter_staged_kernel<Tag, D, F, GT, false, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
-                    c.N, c.pts, d_out, c.lv, p);
+                bin_scatter_staged_kernel<Tag, D, F, GT, false, true, true><<<p.W, kStageBlock, lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p, c.net);
             else
-                bin_scatter_staged_kernel<Tag, D, F, GT, false, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
-                    c.N, c.pts, d_out, c.lv, p);
+                bin_scatter_staged_kernel<Tag, D, F, GT, false, false, true><<<p.W, kStageBlock, lds, c.stream>>>(
+                    c.N, c.pts, d_out, c.lv, p, c.net);
         }
-    } else
-        bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out, c.lv,
-                                                                                                p);
+    } else {
+        trace_begin(c.stream, "bin_scatter", N * (4.0 * D + (p.l1 - p.l0) * F * gs) + counts + payload);
+        if (staged) {
+            if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
+                if (few && dense)
+                    bin_scatter_staged_kernel<Tag, D, F, GT, true, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                        c.N, c.pts, d_out, c.lv, p, c.net);
+                else if (few)
+                    bin_scatter_staged_kernel<Tag, D, F, GT, true, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                        c.N, c.pts, d_out, c.lv, p, c.net);
+                else if (dense)
+                    bin_scatter_staged_kernel<Tag, D, F, GT, false, true><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                        c.N, c.pts, d_out, c.lv, p, c.net);
+                else
+                    bin_scatter_staged_kernel<Tag, D, F, GT, false, false><<<p.W, kStageBlock, staged_lds, c.stream>>>(
+                        c.N, c.pts, d_out, c.lv, p, c.net);
+            }
+        } else
+            bin_scatter_kernel<Tag, D, F, GT><<<p.W, kBinBlock, p.B * sizeof(uint32_t), c.stream>>>(c.N, c.pts, d_out,
+                                                                                                    c.lv, p);
+    }
     trace_end(c.stream);
     if (aux) {
         const hipError_t e = hipStreamWaitEvent(c.stream, aux->join, 0);
@@ -680,6 +809,24 @@ template <class Tag, int D, int F>
 hipError_t binned_adjoint(const EncodeCall& c) {
     BinLayout lay = bin_layout(c.D, c.F, c.N, Tag::simplex, c.lv);
     char* ws = (char*)c.workspace;
+    if (c.net.x || c.net.check_only) {
+        // the fused network backward: checked before anything is launched
+        constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+        if constexpr (F != 2 || D > 3 || stage_ppt<V, false>() < 1 || stage_ppt<V, true>() < 1) {
+            return hipErrorNotSupported;
+        } else {
+            if (!lay.ok || lay.groups != 1 || c.lv.L * F != kNetUnits || c.dout_f16) return hipErrorNotSupported;
+            int B = 0, bmax = 0;  // the one group's buckets, as its plan counts them
+            for (int l = 0; l < lay.L; ++l) {
+                B += lay.nb[l];
+                bmax = lay.nb[l] > bmax ? lay.nb[l] : bmax;
+            }
+            const bool few = bmax <= kStageFewBuckets && V >= 4;
+            const size_t lds = staged_lds_bytes<V, F>(B, bmax, few);
+            if (lds > kStageLdsMax || lds + BwdFrags<kNetUnits>::BYTES > kNetLdsMax) return hipErrorNotSupported;
+        }
+        if (c.net.check_only) return hipSuccess;
+    }
     for (int g = 0; g < lay.groups; ++g) {
         BinPlan p = bin_plan(lay, g, ws);
         uint32_t* totals = (uint32_t*)(ws + lay.off_totals);

@@ -103,15 +103,9 @@ constexpr int kMaxBwdGroups = 512;
 
 template <int DIN>
 struct BwdLayout {
-    // weight fragments, 16 bytes per lane each
-    static constexpr int F_W1 = 0;                      // [4][DIN/32] f16, loaded k order
-    static constexpr int F_W2 = F_W1 + 4 * (DIN / 32);  // [4][2] f16, chained k order
-    static constexpr int F_W3T = F_W2 + 8;              // [4] bf16, loaded k order (outputs padded to 32)
-    static constexpr int F_W2T = F_W3T + 4;             // [4][2] bf16, chained
-    static constexpr int F_W1T = F_W2T + 8;             // [DIN/16][2] bf16, chained
-    static constexpr int NFRAG = F_W1T + 2 * (DIN / 16);
-    static constexpr int FRAG_BYTES = NFRAG * 64 * 16;
-    // per-wave transpose area: one row of 16 points (bf16) per unit
+    // weight fragments (BwdFrags), then a per-wave transpose area: one row of
+    // 16 points (bf16) per unit
+    static constexpr int FRAG_BYTES = BwdFrags<DIN>::BYTES;
     static constexpr int R_DY = 0, R_H2 = 16, R_H1 = 80, R_DA2 = 144, R_DA1 = 208, R_X = 272;
     static constexpr int ROWS = R_X + DIN;
     static constexpr int WAVE_BYTES = ROWS * kPts * 2;
@@ -123,13 +117,16 @@ struct BwdLayout {
     static constexpr int TPW = TILES / kBwdWaves;
 };
 
+// d_x (when not NULL) receives units [0, dx_cols) of each point's input
+// gradient, in rows of dx_stride floats (dx_cols and dx_stride multiples of
+// 4; the full gradient is dx_cols = dx_stride = DIN).
 template <int DIN>
 __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16* __restrict__ x,
                                                       const _Float16* __restrict__ W1,
                                                       const _Float16* __restrict__ W2,
                                                       const _Float16* __restrict__ W3, int d_out,
                                                       const float* __restrict__ d_y, float* __restrict__ d_x,
-                                                      float* __restrict__ partial) {
+                                                      int dx_cols, int dx_stride, float* __restrict__ partial) {
     using Lay = BwdLayout<DIN>;
     constexpr int KS1 = DIN / 32;
     constexpr int TIN = DIN / 16;
@@ -139,45 +136,8 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
     const int lane = tid & 63, r = lane & 15, q = lane >> 4, wv = tid >> 6;
 
     // ---- stage the weight fragments (each wave builds a quarter of them)
-    for (int f = wv; f < Lay::NFRAG; f += kBwdWaves) {
-        uint4 v;
-        if (f < Lay::F_W2) {
-            const int t = (f - Lay::F_W1) / KS1, s = (f - Lay::F_W1) % KS1;
-            h8 a = *reinterpret_cast<const h8*>(W1 + (16 * t + r) * DIN + 32 * s + 8 * q);
-            v = *reinterpret_cast<uint4*>(&a);
-        } else if (f < Lay::F_W3T) {
-            const int t = (f - Lay::F_W2) / 2, s = (f - Lay::F_W2) % 2;
-            h8 a;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = W2[(16 * t + r) * H + 32 * s + k_chain(q, j)];
-            v = *reinterpret_cast<uint4*>(&a);
-        } else if (f < Lay::F_W2T) {
-            const int t = f - Lay::F_W3T;
-            b8 a;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int o = k_load(q, j);
-                a[j] = (__bf16)(o < d_out ? (float)W3[o * H + 16 * t + r] : 0.0f);
-            }
-            v = *reinterpret_cast<uint4*>(&a);
-        } else if (f < Lay::F_W1T) {
-            const int t = (f - Lay::F_W2T) / 2, s = (f - Lay::F_W2T) % 2;
-            b8 a;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = (__bf16)(float)W2[(32 * s + k_chain(q, j)) * H + 16 * t + r];
-            v = *reinterpret_cast<uint4*>(&a);
-        } else {
-            const int t = (f - Lay::F_W1T) / 2, s = (f - Lay::F_W1T) % 2;
-            b8 a;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = (__bf16)(float)W1[(32 * s + k_chain(q, j)) * DIN + 16 * t + r];
-            v = *reinterpret_cast<uint4*>(&a);
-        }
-        frag[f * 64 + lane] = v;
-    }
+    stage_bwd_frags<DIN>(frag, W1, W2, W3, d_out, wv, kBwdWaves, lane);
     __syncthreads();
-    auto fh = [&](int f) { uint4 u = frag[f * 64 + lane]; return *reinterpret_cast<h8*>(&u); };
-    auto fb = [&](int f) { uint4 u = frag[f * 64 + lane]; return *reinterpret_cast<b8*>(&u); };
 
     short* const S0 = reinterpret_cast<short*>(lds + Lay::FRAG_BYTES);
     short* S = S0 + wv * (Lay::WAVE_BYTES / 2);
@@ -193,82 +153,37 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
         const int64_t base = it * per_iter + wv * kPts;
         const int64_t p = base + r;
         const bool valid = p < N;
-        // forward recompute
-        h8 xb[KS1];
-#pragma unroll
-        for (int s = 0; s < KS1; ++s)
-            xb[s] = valid ? *reinterpret_cast<const h8*>(x + p * DIN + 32 * s + 8 * q) : h8{};
-        h4 h1[4], h2[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            f4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < KS1; ++s) c = mma_h(fh(Lay::F_W1 + t * KS1 + s), xb[s], c);
-            h1[t] = relu_h(c);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            f4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < 2; ++s) c = mma_h(fh(Lay::F_W2 + 2 * t + s), cat_h(h1[2 * s], h1[2 * s + 1]), c);
-            h2[t] = relu_h(c);
-        }
-        // incoming gradient, loaded k order (outputs 8q..8q+7)
-        b8 dyb;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int o = k_load(q, j);
-            dyb[j] = (__bf16)((valid && o < d_out) ? d_y[p * d_out + o] : 0.0f);
-        }
-        // dH2 = W3^T dY, masked by the stored activation
-        f4 da2[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            f4 c = mma_b(fb(Lay::F_W3T + t), dyb, f4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int i = 0; i < 4; ++i) c[i] = (float)h2[t][i] > 0.0f ? (float)(__bf16)c[i] : 0.0f;
-            da2[t] = c;
-        }
-        // dH1 = W2^T dA2, masked
-        f4 da1[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            f4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < 2; ++s) c = mma_b(fb(Lay::F_W2T + 2 * t + s), cat_b(da2[2 * s], da2[2 * s + 1]), c);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) c[i] = (float)h1[t][i] > 0.0f ? (float)(__bf16)c[i] : 0.0f;
-            da1[t] = c;
-        }
-        // dX = W1^T dA1
+        BwdTile<DIN> tl;
+        tl.run(frag, lane, x, d_y, d_out, p, valid);
         if (d_x) {
 #pragma unroll
             for (int t = 0; t < TIN; ++t) {
-                f4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < 2; ++s) c = mma_b(fb(Lay::F_W1T + 2 * t + s), cat_b(da1[2 * s], da1[2 * s + 1]), c);
-                if (valid) *reinterpret_cast<f4*>(d_x + p * DIN + 16 * t + 4 * q) = c;
+                if (16 * t >= dx_cols) break;  // uniform
+                const f4 c = tl.dx(frag, lane, t);
+                if (valid && 16 * t + 4 * q < dx_cols) *reinterpret_cast<f4*>(d_x + p * dx_stride + 16 * t + 4 * q) = c;
             }
         }
         // transpose the weight-gradient operands through LDS: row = unit, column = point
         if (q < 2) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) S[(Lay::R_DY + k_load(q, j)) * kPts + r] = __builtin_bit_cast(short, (__bf16)dyb[j]);
+            for (int j = 0; j < 8; ++j)
+                S[(Lay::R_DY + k_load(q, j)) * kPts + r] = __builtin_bit_cast(short, (__bf16)tl.dyb[j]);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int u = 16 * t + 4 * q + i;
-                S[(Lay::R_H2 + u) * kPts + r] = bf_bits((float)h2[t][i]);
-                S[(Lay::R_H1 + u) * kPts + r] = bf_bits((float)h1[t][i]);
-                S[(Lay::R_DA2 + u) * kPts + r] = bf_bits(da2[t][i]);
-                S[(Lay::R_DA1 + u) * kPts + r] = bf_bits(da1[t][i]);
+                S[(Lay::R_H2 + u) * kPts + r] = bf_bits((float)tl.h2[t][i]);
+                S[(Lay::R_H1 + u) * kPts + r] = bf_bits((float)tl.h1[t][i]);
+                S[(Lay::R_DA2 + u) * kPts + r] = bf_bits(tl.da2[t][i]);
+                S[(Lay::R_DA1 + u) * kPts + r] = bf_bits(tl.da1[t][i]);
             }
 #pragma unroll
         for (int s = 0; s < KS1; ++s)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) S[(Lay::R_X + 32 * s + k_load(q, j)) * kPts + r] = bf_bits((float)xb[s][j]);
+            for (int j = 0; j < 8; ++j)
+                S[(Lay::R_X + 32 * s + k_load(q, j)) * kPts + r] = bf_bits((float)tl.xb[s][j]);
         __syncthreads();
         // Weight gradients over the iteration's 64 points: this wave's tiles,
         // k = 32 points per MFMA (lane group q reads 8 points of region
@@ -381,10 +296,11 @@ hipError_t bwd_impl(const MlpCall& c) {
     const int g = bwd_groups(c.N);
     float* part = (float*)c.workspace;
     trace_begin(c.stream, "mlp_bwd",
-                (double)c.N * (2.0 * DIN + 4.0 * c.d_out + (c.d_x ? 4.0 * DIN : 0.0)) + (double)g * Lay::PARTIAL * 4.0);
+                (double)c.N * (2.0 * DIN + 4.0 * c.d_out + (c.d_x ? 4.0 * (c.dx_cols > 0 ? c.dx_cols : DIN) : 0.0)) + (double)g * Lay::PARTIAL * 4.0);
+    const int dx_cols = c.dx_cols > 0 ? c.dx_cols : DIN, dx_stride = c.dx_stride > 0 ? c.dx_stride : DIN;
     mlp_bwd_kernel<DIN><<<g, 256, Lay::LDS_BYTES, c.stream>>>(c.N, (const _Float16*)c.x, (const _Float16*)c.W1,
                                                               (const _Float16*)c.W2, (const _Float16*)c.W3,
-                                                              c.d_out, c.d_y, c.d_x, part);
+                                                              c.d_out, c.d_y, c.d_x, dx_cols, dx_stride, part);
     trace_end(c.stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -334,6 +334,18 @@ inline BinPlan bin_plan(const BinLayout& lay, int g, char* ws) {
     return p;
 }
 
+// The network (d_in -> 64 -> 64 -> d_out) whose input gradient the fused
+// adjoint computes itself: binary16 features x [N][d_in] and weights, the
+// binary32 output gradient d_y [N][d_out].
+struct NetArgs {
+    const _Float16* x;
+    const _Float16 *W1, *W2, *W3;
+    const float* d_y;
+    int d_out;
+    int coarse_stride;
+    int check_only;  // only check that the fused path covers the configuration
+};
+
 struct EncodeCall {
     EncodeOp op;
     int D, F;
@@ -348,6 +360,11 @@ struct EncodeCall {
     float* w;
     void* workspace;  // binned adjoint only
     AdamArgs adam;    // binned adjoint only
+    // binned adjoint only: when net.x is set, the output gradient is the
+    // network's input gradient, computed in the scatter from the features
+    // and the network's output gradient (d_out then holds only the
+    // privatised coarse levels' units, rows of net.coarse_stride floats)
+    NetArgs net;
     LevelArgs lv;
     hipStream_t stream;
 };
@@ -400,6 +417,7 @@ struct MlpCall {
     float* y;
     const float* d_y;
     float* d_x;
+    int dx_cols, dx_stride;  // units of d_x written per point and its row stride (0: all d_in)
     float *dW1, *dW2, *dW3;
     void* workspace;
     hipStream_t stream;

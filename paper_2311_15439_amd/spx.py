@@ -88,6 +88,10 @@ _SIGNATURES = {
     "spx_mlp_fwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P]),
     "spx_mlp_bwd_workspace": (C.c_int, [_P, C.c_int64, _P]),
     "spx_mlp_bwd": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "spx_encode_mlp_bwd_adam": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                          C.c_float, C.c_float, C.c_float, C.c_float, C.c_int64, _P, C.c_size_t,
+                                          _P]),
+    "spx_encode_mlp_bwd_workspace": (C.c_int, [_P, _P, C.c_int64, _P]),
     "spx_mlp_bwd_noalloc": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
 }
 
@@ -461,6 +465,37 @@ def spx_mlp_bwd(mlp: spx_mlp, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, workspace,
                              _dev(dW1, f, "dW1"), _dev(dW2, f, "dW2"), _dev(dW3, f, "dW3"),
                              _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)),
            "spx_mlp_bwd")
+
+
+def spx_encode_mlp_bwd_workspace(enc: Encoding, mlp: spx_mlp, N: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().spx_encode_mlp_bwd_workspace(enc.ref(), C.byref(mlp), N, C.byref(out)),
+           "spx_encode_mlp_bwd_workspace")
+    return int(out.value)
+
+
+def spx_encode_mlp_bwd_adam(enc: Encoding, mlp: spx_mlp, pts, x, W1, W2, W3, d_y, dW1, dW2, dW3, param, m, v,
+                            param_f16=None, *, lr, beta1=0.9, beta2=0.99, eps=1e-15, step, workspace,
+                            stream=None) -> None:
+    """Network backward + encoding adjoint + Adam on the tables, with the
+    network's input gradient computed inside the adjoint's scatter."""
+    torch = _torch()
+    N = pts.shape[0]
+    for t in (param, m, v) + ((param_f16,) if param_f16 is not None else ()):
+        if tuple(t.shape) != enc.table_shape:
+            raise ValueError("table state shape does not match the encoding")
+    if tuple(x.shape) != (N, mlp.d_in) or tuple(d_y.shape) != (N, mlp.d_out):
+        raise ValueError("x must be [N, d_in] and d_y [N, d_out]")
+    h, f = torch.float16, torch.float32
+    _check(lib().spx_encode_mlp_bwd_adam(enc.ref(), C.byref(mlp), N, _dev(pts, f, "pts"), _dev(x, h, "x"),
+                                         _dev(W1, h, "W1"), _dev(W2, h, "W2"), _dev(W3, h, "W3"), _dev(d_y, f, "d_y"),
+                                         _dev(dW1, f, "dW1"), _dev(dW2, f, "dW2"), _dev(dW3, f, "dW3"),
+                                         _dev(param, f, "param"), _dev(m, f, "m"), _dev(v, f, "v"),
+                                         None if param_f16 is None else _dev(param_f16, h, "param_f16"),
+                                         float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                         _dev(workspace, torch.uint8, "workspace"), workspace.numel(),
+                                         _stream(stream)),
+           "spx_encode_mlp_bwd_adam")
 
 
 def spx_mlp_bwd_noalloc(mlp: spx_mlp, x, W1, W2, W3, d_y, d_x, dW1, dW2, dW3, stream=None) -> None:

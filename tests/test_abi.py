@@ -161,3 +161,42 @@ def test_binned_workspace_sizes():
     assert spx.spx_encode_bwd_workspace(g3, 1 << 16) > spx.spx_encode_bwd_workspace(s3, 1 << 16)
     # the largest table still bins (one level per group)
     assert spx.spx_encode_bwd_workspace(spx.Encoding(6, [16] * 32, 26, n_feat=8), 1 << 16) > 0
+
+
+def test_fused_network_backward_coverage_on_host():
+    """spx_encode_mlp_bwd_workspace / _adam decide on the host, before any
+    launch, which configurations the fused network backward covers."""
+    L = spx.lib()
+    fake = C.c_void_p(0x10000)
+    s = C.c_void_p(0)
+    mlp = spx.make_mlp(32, 64, 3)
+    res16 = spx.spx_level_resolutions(16, 1.38, 16)
+    image = spx.Encoding(2, res16, 19, 2, table_dtype=spx.SPX_F16)
+    volume = spx.Encoding(3, spx.spx_level_resolutions(16, 1.32, 16), 19, 2, table_dtype=spx.SPX_F16)
+    for enc, N in [(image, 1 << 20), (volume, 1 << 21), (image, 0), (image, 1)]:
+        # the unfused workspaces plus N rows of the privatised levels' units
+        need = spx.spx_encode_mlp_bwd_workspace(enc, mlp, N)
+        assert need >= spx.spx_encode_bwd_workspace(enc, N) + spx.spx_mlp_bwd_workspace(mlp, N)
+    out = C.c_size_t(0)
+
+    def ws(enc, m=mlp, N=1000):
+        return L.spx_encode_mlp_bwd_workspace(enc.ref(), C.byref(m), N, C.byref(out))
+
+    assert ws(spx.Encoding(4, res16, 14, 2)) == spx.SPX_EUNSUPPORTED                    # n > 3
+    assert ws(spx.Encoding(2, res16[:8], 14, 4)) == spx.SPX_EUNSUPPORTED                # n_feat 4
+    assert ws(spx.Encoding(2, res16[:12], 14, 2)) == spx.SPX_EINVAL                     # d_in != L * F
+    assert ws(image, spx.make_mlp(32, 32, 3)) == spx.SPX_EUNSUPPORTED                   # hidden 32
+    # more buckets than one level group holds (2^26 rows per level, 16 levels)
+    assert ws(spx.Encoding(2, res16, 26, 2)) == spx.SPX_EUNSUPPORTED
+    assert "level group" in spx.spx_last_error()
+    need = spx.spx_encode_mlp_bwd_workspace(image, mlp, 1000)
+
+    def fused(enc=image, N=1000, nbytes=need, wsp=fake, step=1, param=fake):
+        return L.spx_encode_mlp_bwd_adam(enc.ref(), C.byref(mlp), N, fake, fake, fake, fake, fake, fake, fake, fake,
+                                         fake, param, fake, fake, None, 1e-2, 0.9, 0.99, 1e-15, step, wsp, nbytes, s)
+
+    assert fused(nbytes=need - 1) == spx.SPX_EINVAL
+    assert fused(wsp=C.c_void_p(0x10010)) == spx.SPX_EALIGN
+    assert fused(step=0) == spx.SPX_EINVAL
+    assert fused(param=C.c_void_p(0x10004)) == spx.SPX_EALIGN
+    assert fused(enc=spx.Encoding(4, res16, 14, 2)) == spx.SPX_EUNSUPPORTED

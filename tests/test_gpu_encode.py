@@ -341,6 +341,19 @@ def test_bwd_adam_fused_parity(n, res, log2_T, N, cell):
     torch.cuda.synchronize()
     gref, gmag, cnt = oracle.encode_bwd(o, pts, d.astype(np.float64), with_stats=True)
     tolg = (cnt + n + 2) * 2.0 ** -24 * gmag + 1e-30
+    p = adam_problem(p0, m0, v0, gref, tolg, tp, tm, tv, lr, b1, b2, eps, step)
+    assert p is None, p
+    np.testing.assert_array_equal(th.cpu().numpy().view(np.uint16).ravel(),
+                                  oracle.cast_f32_f16(tp.cpu().numpy().ravel()))
+
+
+def adam_problem(p0, m0, v0, gref, tolg, tp, tm, tv, lr, b1, b2, eps, step):
+    """None if the GPU's Adam state (tp, tm, tv) matches the oracle's Adam
+    step from (p0, m0, v0) with the oracle's table gradient gref, each entry
+    of the GPU's gradient being within tolg of gref; otherwise the first
+    failure.  The gradient's error is carried through the update
+    (d m / d g = 1 - b1, d v / d g = 2 (1 - b2) g), on top of the binary32
+    roundings of the step itself."""
     p, m, v, _ = oracle.adam_step(p0.ravel(), gref.ravel().astype(np.float32), m0.ravel(), v0.ravel(),
                                   lr, b1, b2, eps, step)
     gp, gm, gv = (t.cpu().numpy().ravel().astype(np.float64) for t in (tp, tm, tv))
@@ -355,9 +368,9 @@ def test_bwd_adam_fused_parity(n, res, log2_T, N, cell):
              + upd * 0.5 * (tol_v / bc2) / (sv * sv))
     for name, got, ref, tol in [("m", gm, m, tol_m), ("v", gv, v, tol_v), ("p", gp, p, tol_p)]:
         err = np.abs(got - ref)
-        assert (err <= tol).all(), f"{name}: worst err/tol {np.max(err / tol):.3f}"
-    np.testing.assert_array_equal(th.cpu().numpy().view(np.uint16).ravel(),
-                                  oracle.cast_f32_f16(gp.astype(np.float32)))
+        if not (err <= tol).all():
+            return f"{name}: worst err/tol {np.max(err / tol):.3f}"
+    return None
 
 
 def test_bwd_adam_fused_without_points():
