@@ -207,7 +207,8 @@ def _colour_target(w):
 class TrainStep:
     """All device buffers of one training step; launches only library kernels."""
 
-    def __init__(self, w, cell, batches, host_tables, weights, d_out, fused=True, equal_memory=False, layout=0):
+    def __init__(self, w, cell, batches, host_tables, weights, d_out, fused=True, equal_memory=False, layout=0,
+                 fused_bwd=False):
         import torch
         from paper_2311_15439_amd import spx
         self.torch, self.spx = torch, spx
@@ -253,6 +254,11 @@ class TrainStep:
         self.fused = fused
         # the fused encoding + network forward covers 2-/3-D fields of 16 levels x 2 features, hashed tables
         self.fused_fwd = w.n_dims in (2, 3) and D == 32 and w.n_feat == 2 and layout == spx.SPX_LAYOUT_HASHED
+        # the network backward inside the adjoint's scatter (with the tables' Adam step)
+        self.fused_bwd = fused_bwd and fused
+        if self.fused_bwd:
+            self.nws = torch.empty(spx.spx_encode_mlp_bwd_workspace(self.enc, self.mlp, self.N), dtype=torch.uint8,
+                                   device=dev)
 
     @property
     def names(self):
@@ -270,9 +276,16 @@ class TrainStep:
             calls.append(("encode_fwd", lambda: spx.spx_encode_fwd(self.enc, pts, self.tab16, self.feats)))
             calls.append(("mlp_fwd", lambda: spx.spx_mlp_fwd(self.mlp, self.feats, *self.Wv, self.y)))
         calls += self._loss_calls(b, tgt)
-        calls.append(("mlp_bwd", lambda: spx.spx_mlp_bwd(self.mlp, self.feats, *self.Wv, self.dy, self.dfeats,
-                                                         *self.dWv, self.ws)))
-        if self.fused:
+        if self.fused_bwd:
+            calls.append(("encode_mlp_bwd_adam", lambda: spx.spx_encode_mlp_bwd_adam(
+                self.enc, self.mlp, pts, self.feats, *self.Wv, self.dy, *self.dWv, self.master, self.m, self.v,
+                self.tab16, lr=self.lr, beta1=0.9, beta2=0.99, eps=1e-15, step=self.t, workspace=self.nws)))
+        else:
+            calls.append(("mlp_bwd", lambda: spx.spx_mlp_bwd(self.mlp, self.feats, *self.Wv, self.dy, self.dfeats,
+                                                             *self.dWv, self.ws)))
+        if self.fused_bwd:
+            pass
+        elif self.fused:
             # adjoint and Adam on the tables in one pass (no gradient table)
             calls.append(("encode_bwd_adam", lambda: spx.spx_encode_bwd_adam(
                 self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9,
@@ -322,6 +335,9 @@ class TrainStep:
             # fused: the adjoint's inputs plus the dense Adam update's 26 bytes per
             # parameter (read param, m, v; write param, m, v, binary16 copy)
             "encode_bwd_adam": N * (4 * n + 4 * D + L * V * F * 8) + P * 26,
+            # network backward inside the adjoint: features and network output
+            # gradient in (no input gradient stored), the scatter and the Adam update
+            "encode_mlp_bwd_adam": N * (4 * n + 2 * D + 4 * self.d_out + L * V * F * 8) + P * 26,
             "adam_tables": P * 34 if not self.fused else 0,
             "adam_mlp": nw * 34,
         }
@@ -762,9 +778,10 @@ def volume_bench(with_accuracy=True, steps=10, warmup=3):
         p = _points(w, b)
         batches.append((p, _targets(w, p, b)))
     out = {"workload": w.name + f", {w.n_points} points/step, MLP 32-64-64-4"}
-    for cell, name in ((spx.SPX_SIMPLEX, "simplex"), (spx.SPX_GRID, "grid")):
+    for cell, name, fb in ((spx.SPX_SIMPLEX, "simplex", False), (spx.SPX_GRID, "grid", False),
+                           (spx.SPX_SIMPLEX, "simplex_fused_network_backward", True)):
         print(f"# volume: timing {name} step", file=sys.stderr, flush=True)
-        ts = TrainStep(w, cell, batches, host_tables, weights, 4)
+        ts = TrainStep(w, cell, batches, host_tables, weights, 4, fused_bwd=fb)
         ms, per, _, kern = time_steps(ts, steps, warmup)
         out[name] = {"ms_per_step": ms, "points_per_s": ts.N / (ms * 1e-3),
                      "kernels_ms": {k: round(v["avg_ms"] * v["launches_per_step"], 5) for k, v in kern.items()}}
@@ -1118,9 +1135,20 @@ def main():
                    "algorithmic_GB_s": round(v["bytes_per_launch"] / (v["avg_ms"] * 1e-3) / 1e9, 1)}
                for n, v in sorted(kern.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches_per_step"])}
 
+    # the network backward inside the adjoint's scatter (spx_encode_mlp_bwd_adam), same batches
+    del ts
+    torch.cuda.empty_cache()
+    print("# timing the step with the network backward fused into the adjoint", file=sys.stderr, flush=True)
+    tf = TrainStep(w, spx.SPX_SIMPLEX, batches, host_tables, weights, d_out, fused_bwd=True)
+    fms, fper, _, fkern = time_steps(tf, max(5, args.steps // 2), 2)
+    fused_bwd = {"ms_per_step": fms, "step_points_per_s": tf.N / (fms * 1e-3), "vs_separate": ms / fms,
+                 "calls_ms": {k: round(v, 5) for k, v in fper.items()},
+                 "kernels_ms": {k: round(v["avg_ms"] * v["launches_per_step"], 5) for k, v in fkern.items()}}
+    del tf
+    torch.cuda.empty_cache()
+
     grid = None
     if not args.no_grid:
-        del ts
         torch.cuda.empty_cache()
         tg = TrainStep(w, spx.SPX_GRID, batches, host_tables, weights, d_out)
         print("# timing grid step", file=sys.stderr, flush=True)
@@ -1192,6 +1220,7 @@ def main():
                                 "kernels_ms": grid["kernels_ms"]} if grid else None),
         "stream_reference": stream,
         "fused_query": fused_query,
+        "fused_network_backward": fused_bwd,
         "gather_probe_gathers_per_s": probe,
         "encode_sweep": sweep,
         "equal_accuracy": accuracy,
@@ -1247,6 +1276,10 @@ def summary_lines(d):
                    f"{a['sized']['psnr_db']:.2f} vs {a['hashed']['psnr_db']:.2f} dB (grid {a['grid']['psnr_db']:.2f}); "
                    f"step {a['sized']['ms_per_step']:.3f} / {a['hashed']['ms_per_step']:.3f} / "
                    f"{a['grid']['ms_per_step']:.3f} ms (sized / hashed / grid)")
+    fb = d.get("fused_network_backward")
+    if fb:
+        out.append(f"# network backward fused into the adjoint: {fb['ms_per_step']:.3f} ms per step, "
+                   f"{fb['vs_separate']:.3f}x the separate kernels' {d['ms_per_step']:.3f} ms")
     sv = d.get("serving")
     if sv:
         loads = ", ".join(f"{l['load']:.0%}: p50 {l['p50_ms']:.2f} p99 {l['p99_ms']:.2f} ms" for l in sv["loads"])
@@ -1337,6 +1370,10 @@ def headline(d, value, steps, warmup, detail_path):
                                                         _r(a["sized_minus_hashed_db"], 3),
                                                         _r(a.get("sized_minus_grid_db"), 3),
                                                         _r(a.get("sized_speedup_vs_grid"), 3)]
+    fb = d.get("fused_network_backward")
+    if fb:
+        out.append(f"# network backward fused into the adjoint: {fb['ms_per_step']:.3f} ms per step, "
+                   f"{fb['vs_separate']:.3f}x the separate kernels' {d['ms_per_step']:.3f} ms")
     sv = d.get("serving")
     if sv:
         line["serving"] = {"saturation_points_per_s": _r(sv["saturation_points_per_s"]),

@@ -430,21 +430,36 @@ __global__ __launch_bounds__(kStageBlock, NET ? 2 : stage_waves(FEW)) void bin_s
             // level pass ended with a barrier after its records left
             float* tr = reinterpret_cast<float*>(lds + lay.key) + wave * (64 * kNetRow);
             const int r = lane & 15, q = lane >> 4;
+            // Tiles one after another (the scheduling barriers keep the
+            // chains from being interleaved, which would hold several tiles'
+            // activations at once), each tile's inputs loaded while the
+            // previous tile computes: units 0..15 go to the transpose rows
+            // at once, units 16..31 wait in registers.
+            BwdTile<kNetUnits> tl;
+            {
+                const int64_t p = r0 + wave * 64 + r;
+                tl.load(lane, net.x, net.d_y, net.d_out, p, p < hi);
+            }
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
-                // Tiles one after another (the scheduling barriers keep the
-                // four chains from being interleaved, which would hold four
-                // tiles' activations at once): units 0..15 go to the
-                // transpose rows at once, units 16..31 wait in registers.
                 f4 hi16[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const int64_t p = r0 + (int64_t)j * kStageBlock + wave * 64 + 16 * k + r;
-                    BwdTile<kNetUnits> tl;
-                    tl.run(frag, lane, net.x, net.d_y, net.d_out, p, p < hi);
+                    BwdTile<kNetUnits> nx;  // the next tile's inputs (this round's)
+                    const int jn = k == 3 ? j + 1 : j, kn = k == 3 ? 0 : k + 1;
+                    if (jn < PPT) {
+                        const int64_t p = r0 + (int64_t)jn * kStageBlock + wave * 64 + 16 * kn + r;
+                        nx.load(lane, net.x, net.d_y, net.d_out, p, p < hi);
+                    }
+                    tl.compute(frag, lane);
                     *reinterpret_cast<f4*>(tr + (16 * k + r) * kNetRow + 4 * q) = tl.dx(frag, lane, 0);
                     hi16[k] = tl.dx(frag, lane, 1);
                     __builtin_amdgcn_sched_barrier(0);
+                    if (jn < PPT) {
+#pragma unroll
+                        for (int s2 = 0; s2 < BwdFrags<kNetUnits>::KS1; ++s2) tl.xb[s2] = nx.xb[s2];
+                        tl.dyb = nx.dyb;
+                    }
                 }
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -677,6 +692,16 @@ inline size_t staged_lds_bytes(int B, int bmax, bool few) {
     return (few ? stage_lds<V, F, true>(B, bmax) : stage_lds<V, F, false>(B, bmax)).words * sizeof(uint32_t);
 }
 
+// The fused scatter runs in the shape with more points per thread whatever
+// the bucket count: its registers hold the round's network gradients, so it
+// runs one workgroup per CU either way, and the longer rounds give longer
+// runs of records.  (The count pass's shape does not change what it counts:
+// the runs it merges are those of aligned 64-point rows in either shape.)
+template <int V, int F>
+inline size_t net_lds_bytes(int B, int bmax) {
+    return staged_lds_bytes<V, F>(B, bmax, false) + BwdFrags<kNetUnits>::BYTES;
+}
+
 template <class Tag, int D, int F, typename GT>
 hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
     const GT* d_out = (const GT*)c.d_out;
@@ -699,7 +724,7 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
         staged_lds = staged_lds_bytes<V, F>(p.B, p.bmax, few);
         staged = staged_lds <= kStageLdsMax;
     }
-    if (net && (!kNetOk || !staged || staged_lds + BwdFrags<kNetUnits>::BYTES > kNetLdsMax))
+    if (net && (!kNetOk || !staged || net_lds_bytes<V, F>(p.B, p.bmax) > kNetLdsMax))
         return hipErrorNotSupported;  // checked by the caller before any launch
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     // Without a densely stored level the staged kernels never compute dense
@@ -762,14 +787,8 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
                     N * (4.0 * D + 2.0 * kNetUnits + 4.0 * c.net.d_out) + counts + payload);
         if constexpr (kNetOk && std::is_same<GT, float>::value && stage_ppt<V, false>() >= 1 &&
                       stage_ppt<V, true>() >= 1) {
-            const size_t lds = staged_lds + BwdFrags<kNetUnits>::BYTES;
-            if (few && dense)
-                bin_scatter_staged_kernel<Tag, D, F, GT, true, true, true><<<p.W, kStageBlock, lds, c.stream>>>(
-                    c.N, c.pts, d_out, c.lv, p, c.net);
-            else if (few)
-                bin_scatter_staged_kernel<Tag, D, F, GT, true, false, true><<<p.W, kStageBlock, lds, c.stream>>>(
-                    c.N, c.pts, d_out, c.lv, p, c.net);
-            else if (dense)
+            const size_t lds = net_lds_bytes<V, F>(p.B, p.bmax);
+            if (dense)
                 bin_scatter_staged_kernel<Tag, D, F, GT, false, true, true><<<p.W, kStageBlock, lds, c.stream>>>(
                     c.N, c.pts, d_out, c.lv, p, c.net);
             else
@@ -822,8 +841,8 @@ hipError_t binned_adjoint(const EncodeCall& c) {
                 bmax = lay.nb[l] > bmax ? lay.nb[l] : bmax;
             }
             const bool few = bmax <= kStageFewBuckets && V >= 4;
-            const size_t lds = staged_lds_bytes<V, F>(B, bmax, few);
-            if (lds > kStageLdsMax || lds + BwdFrags<kNetUnits>::BYTES > kNetLdsMax) return hipErrorNotSupported;
+            if (staged_lds_bytes<V, F>(B, bmax, few) > kStageLdsMax || net_lds_bytes<V, F>(B, bmax) > kNetLdsMax)
+                return hipErrorNotSupported;
         }
         if (c.net.check_only) return hipSuccess;
     }

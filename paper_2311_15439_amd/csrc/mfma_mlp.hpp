@@ -125,10 +125,26 @@ struct BwdTile {
 
     __device__ __forceinline__ void run(const uint4* frag, int lane, const _Float16* __restrict__ x,
                                         const float* __restrict__ d_y, int d_out, int64_t p, bool valid) {
+        load(lane, x, d_y, d_out, p, valid);
+        compute(frag, lane);
+    }
+
+    // the tile's inputs: features and incoming gradient (dyb in loaded k
+    // order, outputs 8q..8q+7), zero for points past the end
+    __device__ __forceinline__ void load(int lane, const _Float16* __restrict__ x, const float* __restrict__ d_y,
+                                         int d_out, int64_t p, bool valid) {
         const int q = lane >> 4;
 #pragma unroll
         for (int s = 0; s < Fr::KS1; ++s)
             xb[s] = valid ? *reinterpret_cast<const h8*>(x + p * DIN + 32 * s + 8 * q) : h8{};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int o = k_load(q, j);
+            dyb[j] = (__bf16)((valid && o < d_out) ? d_y[p * d_out + o] : 0.0f);
+        }
+    }
+
+    __device__ __forceinline__ void compute(const uint4* frag, int lane) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             f4 c = {0.f, 0.f, 0.f, 0.f};
@@ -142,12 +158,6 @@ struct BwdTile {
 #pragma unroll
             for (int s = 0; s < 2; ++s) c = mma_h(fh(frag, Fr::F_W2 + 2 * t + s, lane), cat_h(h1[2 * s], h1[2 * s + 1]), c);
             h2[t] = relu_h(c);
-        }
-        // incoming gradient, loaded k order (outputs 8q..8q+7)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int o = k_load(q, j);
-            dyb[j] = (__bf16)((valid && o < d_out) ? d_y[p * d_out + o] : 0.0f);
         }
         // dH2 = W3^T dY, masked by the stored activation
 #pragma unroll
