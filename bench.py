@@ -1372,8 +1372,7 @@ def headline(d, value, steps, warmup, detail_path):
                                                         _r(a.get("sized_speedup_vs_grid"), 3)]
     fb = d.get("fused_network_backward")
     if fb:
-        out.append(f"# network backward fused into the adjoint: {fb['ms_per_step']:.3f} ms per step, "
-                   f"{fb['vs_separate']:.3f}x the separate kernels' {d['ms_per_step']:.3f} ms")
+        line["fused_network_backward"] = {"ms_per_step": _r(fb["ms_per_step"]), "vs_separate": _r(fb["vs_separate"], 3)}
     sv = d.get("serving")
     if sv:
         line["serving"] = {"saturation_points_per_s": _r(sv["saturation_points_per_s"]),

@@ -130,6 +130,7 @@ def _fake_detail():
                                      "sized_memory_fraction": 0.43, "sized_minus_hashed_db": -0.1,
                                      "sized_minus_grid_db": -0.2, "sized_speedup_vs_grid": 1.29}
                             for w in (inputs.IMAGE_2D, inputs.VOLUME_3D)},
+        "fused_network_backward": {"ms_per_step": 1.716, "vs_separate": 0.955},
         "serving": {"saturation_points_per_s": 4.2e8,
                     "loads": [{"load": 0.5, "p50_ms": 1.4, "p99_ms": 5.2, "points_per_s": 2e8},
                               {"load": 0.8, "p50_ms": 2.1, "p99_ms": 5.2, "points_per_s": 3.3e8}]},
@@ -151,4 +152,5 @@ def test_headline_is_compact_json():
     r = back["roofline"]
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and 0 < r["frac"] <= 1
     assert back["cpu_baseline"]["cores"] == 16 and back["cpu_baseline"]["cpu_model"]
+    assert back["fused_network_backward"]["vs_separate"] == 0.955
     assert all(ln.startswith("# ") for ln in bench.summary_lines(d))
