@@ -38,6 +38,10 @@ PER_FILE = {
     # perform the same binary32 operation sequence
     "optim.hip": ["-ffp-contract=off"],
     "field_query.hip": ["-ffp-contract=off"],
+    # the network backward's products feed vector code: their results go to
+    # ordinary registers instead of accumulation registers (which took one
+    # copy instruction per result value)
+    "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

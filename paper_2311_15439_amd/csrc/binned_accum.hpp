@@ -63,9 +63,14 @@ __device__ __forceinline__ void lds_add_row(float* row, const float (&v)[F]) {
 }
 
 constexpr int kAccBlock = 1024;  // one workgroup per CU (128 KiB accumulator)
-// records loaded per thread before their LDS adds (two were no faster and
-// spilled registers beside the preloaded state)
-constexpr int kAccUnroll = 1;
+// Records loaded per thread before their LDS adds.  With the fused Adam
+// step one: the preloaded state holds 96 registers through the record
+// phase, and two records were no faster and spilled.  Without it (the
+// gradient-table variant) the registers are free and four loads per thread
+// are in flight at once: a bucket's record phase is a loop of dependent
+// load-then-add steps, paced by the loads' latency.
+template <bool ADAM>
+constexpr int acc_unroll() { return ADAM ? 1 : 4; }
 
 // Adam update of four parameters with their summed gradients (the same
 // binary32 operation sequence as the standalone Adam kernel).
@@ -198,19 +203,22 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
         r1 = r0 + (uint32_t)(n * (uint64_t)(part + 1) / (uint64_t)K);
         r0 = r0 + (uint32_t)(n * (uint64_t)part / (uint64_t)K);
     }
-    // kAccUnroll records per thread in flight before their LDS adds; the
-    // loop bounds are uniform over the workgroup (lanes past the end idle)
-    for (uint32_t rb = r0; rb < r1; rb += kAccUnroll * kAccBlock) {
-        BinRec<F> rec[kAccUnroll];
-        bool ok[kAccUnroll];
+    // U records per thread in flight before their LDS adds; the loop bounds
+    // are uniform over the workgroup (lanes past the end idle).  The loads
+    // are unconditional (a lane past the end rereads record rb, which
+    // exists) so that all of them are issued before the first wait.
+    constexpr int U = acc_unroll<ADAM>();
+    for (uint32_t rb = r0; rb < r1; rb += U * kAccBlock) {
+        BinRec<F> rec[U];
+        bool ok[U];
 #pragma unroll
-        for (int u = 0; u < kAccUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             const uint32_t r = rb + threadIdx.x + u * kAccBlock;
             ok[u] = r < r1;
-            if (ok[u]) rec[u] = recs[r];
+            rec[u] = recs[ok[u] ? r : rb];
         }
 #pragma unroll
-        for (int u = 0; u < kAccUnroll; ++u) add_record_wave<F>(acc, ok[u], rec[u]);
+        for (int u = 0; u < U; ++u) add_record_wave<F>(acc, ok[u], rec[u]);
     }
     __syncthreads();
     if (K > 1) {  // a part of a split bucket: its sums go to its partial slice

@@ -407,8 +407,15 @@ __global__ __launch_bounds__(kStageBlock, NET ? 2 : stage_waves(FEW)) void bin_s
     // NET: the network's weight fragments, after the staging layout
     const uint4* frag = reinterpret_cast<const uint4*>(lds + lay.words);
     if constexpr (NET) {
-        stage_bwd_frags<kNetUnits>(reinterpret_cast<uint4*>(lds + lay.words), net.W1, net.W2, net.W3, net.d_out,
-                                   wave, kStageBlock / 64, lane);
+        // from a copy of the weights in the staging area (free until the first level pass)
+        static_assert(raw_copy_bytes<kNetUnits, kStageBlock>() <= kStageBlock * PPT * V * (1 + F) * 4,
+                      "weights exceed the staging area");
+        uint4* raw = reinterpret_cast<uint4*>(lds + lay.key);
+        copy_weights_lds<kNetUnits, kStageBlock>(raw, net.W1, net.W2, net.W3, net.d_out, tid);
+        __syncthreads();
+        const _Float16* w = reinterpret_cast<const _Float16*>(raw);
+        stage_bwd_frags<kNetUnits>(reinterpret_cast<uint4*>(lds + lay.words), w, w + H * kNetUnits,
+                                   w + H * kNetUnits + H * H, net.d_out, wave, kStageBlock / 64, lane);
         __syncthreads();
     }
     BinRec<F>* __restrict__ recs = reinterpret_cast<BinRec<F>*>(plan.recs);

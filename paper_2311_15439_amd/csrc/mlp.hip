@@ -135,11 +135,18 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
     const int tid = threadIdx.x;
     const int lane = tid & 63, r = lane & 15, q = lane >> 4, wv = tid >> 6;
 
-    // ---- stage the weight fragments (each wave builds a quarter of them)
-    stage_bwd_frags<DIN>(frag, W1, W2, W3, d_out, wv, kBwdWaves, lane);
-    __syncthreads();
-
     short* const S0 = reinterpret_cast<short*>(lds + Lay::FRAG_BYTES);
+    // ---- stage the weight fragments (each wave builds a quarter of them)
+    // from a copy of the weights in the transpose area, free until the loop
+    static_assert(raw_copy_bytes<DIN, 64 * kBwdWaves>() <= kBwdWaves * Lay::WAVE_BYTES, "weights exceed the transpose area");
+    {
+        uint4* raw = reinterpret_cast<uint4*>(S0);
+        copy_weights_lds<DIN, 64 * kBwdWaves>(raw, W1, W2, W3, d_out, tid);
+        __syncthreads();
+        const _Float16* w = reinterpret_cast<const _Float16*>(raw);
+        stage_bwd_frags<DIN>(frag, w, w + H * DIN, w + H * DIN + H * H, d_out, wv, kBwdWaves, lane);
+        __syncthreads();
+    }
     short* S = S0 + wv * (Lay::WAVE_BYTES / 2);
     static_assert(Lay::TILES % kBwdWaves == 0, "tiles must split evenly over the waves");
 
@@ -149,12 +156,24 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
 
     const int64_t per_iter = (int64_t)kBwdWaves * kPts;
     const int64_t iters = (N + per_iter - 1) / per_iter;
+    // Each iteration's inputs are loaded during the previous iteration's
+    // products (with two waves per SIMD the loads' latency is otherwise the
+    // loop's time).  A point past the end loads zeros.
+    BwdTile<DIN> tl;
+    {
+        const int64_t p = (int64_t)blockIdx.x * per_iter + wv * kPts + r;
+        tl.load(lane, x, d_y, d_out, p, p < N);
+    }
     for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
         const int64_t base = it * per_iter + wv * kPts;
         const int64_t p = base + r;
         const bool valid = p < N;
-        BwdTile<DIN> tl;
-        tl.run(frag, lane, x, d_y, d_out, p, valid);
+        BwdTile<DIN> nx;
+        {
+            const int64_t pn = p + (int64_t)gridDim.x * per_iter;
+            nx.load(lane, x, d_y, d_out, pn, pn < N);
+        }
+        tl.compute(frag, lane);
         if (d_x) {
 #pragma unroll
             for (int t = 0; t < TIN; ++t) {
@@ -170,15 +189,22 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
                 S[(Lay::R_DY + k_load(q, j)) * kPts + r] = __builtin_bit_cast(short, (__bf16)tl.dyb[j]);
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t) {
+            // the hidden gradients are bfloat16 pairs already: their halves
+            // are written as they are (taken from the words with integer
+            // shifts; element reads of the bfloat16 vector through a bit
+            // cast were compiled to the low half for every element)
+            const u2 g2 = __builtin_bit_cast(u2, tl.da2[t]), g1 = __builtin_bit_cast(u2, tl.da1[t]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int u = 16 * t + 4 * q + i;
+                const int sh = 16 * (i & 1);
                 S[(Lay::R_H2 + u) * kPts + r] = bf_bits((float)tl.h2[t][i]);
                 S[(Lay::R_H1 + u) * kPts + r] = bf_bits((float)tl.h1[t][i]);
-                S[(Lay::R_DA2 + u) * kPts + r] = bf_bits(tl.da2[t][i]);
-                S[(Lay::R_DA1 + u) * kPts + r] = bf_bits(tl.da1[t][i]);
+                S[(Lay::R_DA2 + u) * kPts + r] = (short)(g2[i >> 1] >> sh);
+                S[(Lay::R_DA1 + u) * kPts + r] = (short)(g1[i >> 1] >> sh);
             }
+        }
 #pragma unroll
         for (int s = 0; s < KS1; ++s)
 #pragma unroll
@@ -211,6 +237,9 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(int64_t N, const _Float16*
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int s = 0; s < KS1; ++s) tl.xb[s] = nx.xb[s];
+        tl.dyb = nx.dyb;
     }
 
     // ---- each wave writes its own tiles of this group's partial
