@@ -134,10 +134,14 @@ __global__ __launch_bounds__(kBinBlock) void bin_count_kernel(int64_t N, const f
 }
 
 // Per bucket: exclusive prefix of the counts over workgroups, and the total.
-// A block handles 64 buckets; 16 threads per bucket each sum a contiguous
-// segment of workgroups, the 16 segment sums are scanned in LDS, and each
-// thread then rewrites its segment as an exclusive prefix.
+// A block handles 64 buckets; 16 threads per bucket each take a contiguous
+// segment of workgroups (at most 32: W <= 512), the 16 segment sums are
+// scanned in LDS, and each thread then rewrites its segment as an exclusive
+// prefix.  A thread's counts are loaded once, all at once (unconditional
+// loads: a slot past its segment or a bucket past B reads entry 0 and is
+// then taken as zero), and kept in registers between the two passes.
 constexpr int kColBuckets = 64, kColSegs = 16;
+constexpr int kColPer = 512 / kColSegs;  // workgroups per segment at most
 static __global__ __launch_bounds__(kColBuckets * kColSegs) void bin_colscan_kernel(BinPlan plan,
                                                                                   uint32_t* __restrict__ totals) {
     __shared__ uint32_t seg[kColSegs][kColBuckets];
@@ -145,19 +149,25 @@ static __global__ __launch_bounds__(kColBuckets * kColSegs) void bin_colscan_ker
     const int b = blockIdx.x * kColBuckets + lb;
     const int per = (plan.W + kColSegs - 1) / kColSegs;
     const int w0 = sg * per, w1 = w0 + per < plan.W ? w0 + per : plan.W;
+    uint32_t v[kColPer];
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) {
+        const bool in = b < plan.B && w0 + k < w1;
+        v[k] = plan.counts[in ? (size_t)(w0 + k) * plan.B + b : 0];
+        v[k] = in ? v[k] : 0u;
+    }
     uint32_t s = 0;
-    if (b < plan.B)
-        for (int w = w0; w < w1; ++w) s += plan.counts[(size_t)w * plan.B + b];
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) s += v[k];
     seg[sg][lb] = s;
     __syncthreads();
     uint32_t run = 0;
     for (int k = 0; k < sg; ++k) run += seg[k][lb];
     if (b < plan.B) {
-        for (int w = w0; w < w1; ++w) {
-            uint32_t* c = plan.counts + (size_t)w * plan.B + b;
-            const uint32_t v = *c;
-            *c = run;
-            run += v;
+#pragma unroll
+        for (int k = 0; k < kColPer; ++k) {
+            if (w0 + k < w1) plan.counts[(size_t)(w0 + k) * plan.B + b] = run;
+            run += v[k];
         }
         if (sg == kColSegs - 1) totals[b] = run;
     }
@@ -670,17 +680,26 @@ __global__ __launch_bounds__(kBinBlock) void bin_coarse_kernel(int64_t N, const 
 }
 
 // Sum of the workgroups' dense partials.  A block owns 64 entries; 16
-// thread rows each add a contiguous segment of workgroups, and the segment
-// sums are added in order (the result does not depend on scheduling).
+// thread rows each add a contiguous segment of workgroups (at most 32), and
+// the segment sums are added in order (the result does not depend on
+// scheduling).  A thread's partials are loaded all at once (unconditional
+// loads, as in the column scan) and then added in workgroup order.
 static __global__ __launch_bounds__(kColBuckets * kColSegs) void bin_coarse_reduce_kernel(BinPlan plan, int n) {
     __shared__ float seg[kColSegs][kColBuckets];
     const int li = threadIdx.x % kColBuckets, sg = threadIdx.x / kColBuckets;
     const int i = blockIdx.x * kColBuckets + li;
     const int per = (plan.W + kColSegs - 1) / kColSegs;
     const int w0 = sg * per, w1 = w0 + per < plan.W ? w0 + per : plan.W;
+    float v[kColPer];
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k) {
+        const bool in = i < n && w0 + k < w1;
+        v[k] = plan.partial[in ? (size_t)(w0 + k) * n + i : 0];
+    }
     float s = 0.0f;
-    if (i < n)
-        for (int w = w0; w < w1; ++w) s += plan.partial[(size_t)w * n + i];
+#pragma unroll
+    for (int k = 0; k < kColPer; ++k)
+        if (i < n && w0 + k < w1) s += v[k];
     seg[sg][li] = s;
     __syncthreads();
     if (sg != 0 || i >= n) return;

@@ -282,9 +282,20 @@ __global__ __launch_bounds__(kRedOut * kRedSeg) void mlp_reduce_kernel(const flo
     const int per = (groups + kRedSeg - 1) / kRedSeg;
     const int g0 = sg * per < groups ? sg * per : groups;
     const int g1 = g0 + per < groups ? g0 + per : groups;
+    // the segment's partials loaded all at once (unconditional loads: a
+    // slot past the segment reads entry 0 and is not added), then added in
+    // workgroup order
+    constexpr int kPer = kMaxBwdGroups / kRedSeg;
+    float v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const bool in = i < PARTIAL && g0 + k < g1;
+        v[k] = partial[in ? (size_t)(g0 + k) * PARTIAL + i : 0];
+    }
     float s = 0.0f;
-    if (i < PARTIAL)
-        for (int g = g0; g < g1; ++g) s += partial[(size_t)g * PARTIAL + i];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+        if (i < PARTIAL && g0 + k < g1) s += v[k];
     part[sg][o] = s;
     __syncthreads();
     if (sg != 0 || i >= PARTIAL) return;
