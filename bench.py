@@ -256,6 +256,13 @@ class TrainStep:
         self.fused_fwd = w.n_dims in (2, 3) and D == 32 and w.n_feat == 2 and layout == spx.SPX_LAYOUT_HASHED
         # the network backward inside the adjoint's scatter (with the tables' Adam step)
         self.fused_bwd = fused_bwd and fused
+        # the adjoint's counting pass (it needs only the points) on a second
+        # stream beside the forward and the network, joined by an event
+        # before the adjoint (spx_encode_bwd_prepare, then the *_prepared call)
+        self.prepare = fused and not self.fused_bwd
+        if self.prepare:
+            self.side = torch.cuda.Stream()  # default priority
+            self.ev_fork, self.ev_join = torch.cuda.Event(), torch.cuda.Event()
         if self.fused_bwd:
             self.nws = torch.empty(spx.spx_encode_mlp_bwd_workspace(self.enc, self.mlp, self.N), dtype=torch.uint8,
                                    device=dev)
@@ -269,6 +276,16 @@ class TrainStep:
         spx = self.spx
         pts, tgt = self.batches[b % len(self.batches)]
         calls = []
+        if self.prepare:
+            def fork():
+                import torch
+                # the side stream starts after everything issued so far (the
+                # previous step's adjoint still reads the workspace)
+                self.ev_fork.record(torch.cuda.current_stream())
+                self.side.wait_event(self.ev_fork)
+                spx.spx_encode_bwd_prepare(self.enc, pts, self.bws, stream=self.side)
+                self.ev_join.record(self.side)
+            calls.append(("encode_bwd_prepare", fork))
         if self.fused_fwd:
             calls.append(("encode_mlp_fwd", lambda: spx.spx_encode_mlp_fwd(self.enc, self.mlp, pts, self.tab16, *self.Wv,
                                                                            self.y, feats=self.feats)))
@@ -286,10 +303,15 @@ class TrainStep:
         if self.fused_bwd:
             pass
         elif self.fused:
-            # adjoint and Adam on the tables in one pass (no gradient table)
-            calls.append(("encode_bwd_adam", lambda: spx.spx_encode_bwd_adam(
-                self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9,
-                beta2=0.99, eps=1e-15, step=self.t, workspace=self.bws)))
+            # adjoint and Adam on the tables in one pass (no gradient table),
+            # after the counting pass on the side stream
+            def bwd_adam():
+                import torch
+                torch.cuda.current_stream().wait_event(self.ev_join)
+                spx.spx_encode_bwd_adam_prepared(
+                    self.enc, pts, self.dfeats, self.master, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9,
+                    beta2=0.99, eps=1e-15, step=self.t, workspace=self.bws)
+            calls.append(("encode_bwd_adam", bwd_adam))
         else:
             calls.append(("encode_bwd", lambda: spx.spx_encode_bwd(self.enc, pts, self.dfeats, self.grad, self.bws)))
             calls.append(("adam_tables", lambda: spx.spx_adam_step(
@@ -324,6 +346,7 @@ class TrainStep:
         nw = self.Wm.numel()
         D = L * F
         return {
+            "encode_bwd_prepare": 0,  # its kernels run on the side stream and are listed by name
             "encode_fwd": N * (4 * n + L * V * F * 2 + D * 2),
             "encode_mlp_fwd": N * (4 * n + L * V * F * 2 + D * 2 + 4 * self.d_out),
             "mlp_fwd": N * (2 * D + 4 * self.d_out),
@@ -562,9 +585,12 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
     """Encoding alone, simplex vs the 2^n grid on identical points and tables:
     the image workload, the volume workload (n=3, L=16, T=2^19, 2^21 ray
     samples) and the dimension sweep (n=2..6, L=8, T=2^20, 2^20 uniform
-    points).  Forward, and forward + binned adjoint (with the gradient
-    clearing, timed on its own too); median and p10/p90 over per-repetition
-    events.  Gather fractions are the measured random-gather ceiling's time
+    points).  Forward, and forward + binned adjoint with the gradient
+    clearing: in order (`fwd_bwd`, each part timed on its own too; the
+    figure the rates and fractions use), and with the adjoint's counting
+    pass, which needs only the points, on a second stream beside the forward
+    (`fwd_bwd_pipelined`); median and p10/p90 over per-repetition events.  Gather
+    fractions are the measured random-gather ceiling's time
     (encode_gather_ceiling) over the kernel's time; forward + adjoint touch
     every row twice."""
     import torch
@@ -619,6 +645,29 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
                 spx.spx_encode_bwd(enc, pts, dout, grad, ws)
                 ev[r][4].record()
             torch.cuda.synchronize()
+            # forward + adjoint with the adjoint's counting pass (points only) on
+            # a second stream beside the forward, joined before the adjoint
+            side = torch.cuda.Stream()  # default priority
+            pev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+            fork = [torch.cuda.Event() for _ in range(reps)]
+            join = [torch.cuda.Event() for _ in range(reps)]
+            main = torch.cuda.current_stream()
+            for r in range(warm + reps):
+                rr = r - warm
+                if rr >= 0:
+                    pev[rr][0].record()
+                fork[rr % reps].record(main)
+                side.wait_event(fork[rr % reps])
+                spx.spx_encode_bwd_prepare(enc, pts, ws, stream=side)
+                join[rr % reps].record(side)
+                spx.spx_encode_fwd(enc, pts, tab, feats)
+                grad.zero_()
+                main.wait_event(join[rr % reps])
+                spx.spx_encode_bwd_prepared(enc, pts, dout, grad, ws)
+                if rr >= 0:
+                    pev[rr][1].record()
+            torch.cuda.synchronize()
+            pipelined = _quantiles([e[0].elapsed_time(e[1]) for e in pev])
             # gradient with respect to the points (same rows as the forward)
             dpts = torch.empty((N, w.n_dims), dtype=torch.float32, device=dev)
             ig_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -652,6 +701,7 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
             V = enc.n_vertices
             gathers = N * w.n_levels * V
             row[cname] = {"fwd": fq, "zero_grad": _quantiles(z), "bwd": _quantiles(b), "fwd_bwd": tq,
+                          "fwd_bwd_pipelined": pipelined,
                           "gather_twin": wq if f16 else None, "bwd_kernels": bwd_kernels,
                           "input_grad_ms": input_grad_ms,
                           "fwd_points_per_s": N / (fq["median_ms"] * 1e-3),

@@ -245,6 +245,45 @@ spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* 
                                size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * The part of the binned adjoint (Sec. 5 step (e)) that depends only on the
+ * points: which slot range each contribution falls in, counted per
+ * workgroup of the adjoint's scatter and turned into every record's place
+ * in the workspace (for the first level group; a configuration with more
+ * than one group counts the others in the adjoint call itself).  It exists
+ * so that a caller can issue it on a second stream while the forward and
+ * the network run (it needs no gradient), and then call
+ * spx_encode_bwd_prepared or spx_encode_bwd_adam_prepared, which skip it.
+ *   pts, N      the points the adjoint will be called with.
+ *   workspace   as spx_encode_bwd (required), 256-byte aligned; the
+ *               prepared adjoint must get the same workspace, encoding, N
+ *               and unchanged points, and the caller orders the two calls
+ *               (an event recorded after this call on its stream, waited on
+ *               by the adjoint's stream), and keeps other adjoint calls
+ *               that use this workspace from running in between.
+ * N = 0 is a no-op.
+ */
+spx_status spx_encode_bwd_prepare(const spx_encoding* enc, int64_t N, const float* pts, void* workspace,
+                                  size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * spx_encode_bwd (binned: workspace required) after spx_encode_bwd_prepare
+ * on the same encoding, N, points and workspace: the same result, without
+ * the counting it did.
+ */
+spx_status spx_encode_bwd_prepared(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                                   int32_t d_out_dtype, float* d_tables, void* workspace, size_t workspace_bytes,
+                                   hipStream_t stream);
+
+/*
+ * spx_encode_bwd_adam after spx_encode_bwd_prepare on the same encoding, N,
+ * points and workspace: the same result, without the counting it did.
+ */
+spx_status spx_encode_bwd_adam_prepared(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                                        int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
+                                        float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
+                                        size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Lookup introspection for parity tests: the slot and the binary32 weight
  * of every vertex, from the same code the forward and adjoint use.
  *   idx  device [N][L][V] uint32 slots (V = n+1, or 2^n for the grid whose

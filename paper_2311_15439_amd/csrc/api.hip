@@ -380,9 +380,32 @@ spx_status spx_encode_bwd_workspace(const spx_encoding* enc, int64_t N, size_t* 
     return SPX_OK;
 }
 
-spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
-                          int32_t d_out_dtype, float* d_tables, void* workspace, size_t workspace_bytes,
-                          hipStream_t stream) {
+// the workspace checks of every binned-adjoint call
+static spx_status check_workspace(const spx_encoding* enc, int64_t N, const void* workspace, size_t workspace_bytes) {
+    spx::BinLayout lay = layout_for(enc, N);
+    if (!lay.ok) return fail(SPX_EUNSUPPORTED, "configuration too large for the binned adjoint");
+    if (!workspace || workspace_bytes < lay.total_bytes)
+        return fail(SPX_EINVAL, "workspace of %zu bytes needed, %zu given", lay.total_bytes, workspace_bytes);
+    if (!aligned(workspace, 256)) return fail(SPX_EALIGN, "workspace not 256-byte aligned");
+    return SPX_OK;
+}
+
+spx_status spx_encode_bwd_prepare(const spx_encoding* enc, int64_t N, const float* pts, void* workspace,
+                                  size_t workspace_bytes, hipStream_t stream) {
+    spx_status st = check_encoding(enc);
+    if (st) return st;
+    if ((st = check_points(N, pts))) return st;
+    if (N == 0) return SPX_OK;
+    if ((st = check_workspace(enc, N, workspace, workspace_bytes))) return st;
+    spx::EncodeCall c = base_call(enc, N, pts, stream);
+    c.op = spx::EncodeOp::AdjointPrepare;
+    c.workspace = workspace;
+    return from_hip(run(enc, c), "spx_encode_bwd_prepare launch");
+}
+
+static spx_status encode_bwd_impl(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                                  int32_t d_out_dtype, float* d_tables, void* workspace, size_t workspace_bytes,
+                                  hipStream_t stream, bool prepared) {
     spx_status st = check_encoding(enc);
     if (st) return st;
     if ((st = check_points(N, pts))) return st;
@@ -403,10 +426,24 @@ spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, 
         c.op = spx::EncodeOp::AdjointBinned;
         c.workspace = workspace;
     }
+    if (prepared && !workspace) return fail(SPX_EINVAL, "a prepared adjoint needs its workspace");
+    c.prepared = prepared;
     c.dout_f16 = d_out_dtype == SPX_F16;
     c.d_out = d_out;
     c.d_tables = d_tables;
-    return from_hip(run(enc, c), "spx_encode_bwd launch");
+    return from_hip(run(enc, c), prepared ? "spx_encode_bwd_prepared launch" : "spx_encode_bwd launch");
+}
+
+spx_status spx_encode_bwd(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                          int32_t d_out_dtype, float* d_tables, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream) {
+    return encode_bwd_impl(enc, N, pts, d_out, d_out_dtype, d_tables, workspace, workspace_bytes, stream, false);
+}
+
+spx_status spx_encode_bwd_prepared(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                                   int32_t d_out_dtype, float* d_tables, void* workspace, size_t workspace_bytes,
+                                   hipStream_t stream) {
+    return encode_bwd_impl(enc, N, pts, d_out, d_out_dtype, d_tables, workspace, workspace_bytes, stream, true);
 }
 
 static spx_status check_adam(const float* param, const float* m, const float* v, const uint16_t* param_f16,
@@ -437,10 +474,10 @@ static spx::AdamArgs adam_args(float* param, float* m, float* v, uint16_t* param
     return a;
 }
 
-spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
-                               int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
-                               float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
-                               size_t workspace_bytes, hipStream_t stream) {
+static spx_status encode_bwd_adam_impl(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                                       int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
+                                       float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
+                                       size_t workspace_bytes, hipStream_t stream, bool prepared) {
     spx_status st = check_encoding(enc);
     if (st) return st;
     if ((st = check_points(N, pts))) return st;
@@ -460,7 +497,24 @@ spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* 
     c.dout_f16 = d_out_dtype == SPX_F16;
     c.d_out = d_out;
     c.adam = adam_args(param, m, v, param_f16, lr, beta1, beta2, eps, step);
-    return from_hip(run(enc, c), "spx_encode_bwd_adam launch");
+    c.prepared = prepared;
+    return from_hip(run(enc, c), prepared ? "spx_encode_bwd_adam_prepared launch" : "spx_encode_bwd_adam launch");
+}
+
+spx_status spx_encode_bwd_adam(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                               int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
+                               float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream) {
+    return encode_bwd_adam_impl(enc, N, pts, d_out, d_out_dtype, param, m, v, param_f16, lr, beta1, beta2, eps, step,
+                                workspace, workspace_bytes, stream, false);
+}
+
+spx_status spx_encode_bwd_adam_prepared(const spx_encoding* enc, int64_t N, const float* pts, const void* d_out,
+                                        int32_t d_out_dtype, float* param, float* m, float* v, uint16_t* param_f16,
+                                        float lr, float beta1, float beta2, float eps, int64_t step, void* workspace,
+                                        size_t workspace_bytes, hipStream_t stream) {
+    return encode_bwd_adam_impl(enc, N, pts, d_out, d_out_dtype, param, m, v, param_f16, lr, beta1, beta2, eps, step,
+                                workspace, workspace_bytes, stream, true);
 }
 
 spx_status spx_encode_debug(const spx_encoding* enc, int64_t N, const float* pts, uint32_t* idx, float* w,

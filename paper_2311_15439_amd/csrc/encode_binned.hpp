@@ -728,35 +728,36 @@ inline size_t net_lds_bytes(int B, int bmax) {
     return staged_lds_bytes<V, F>(B, bmax, false) + BwdFrags<kNetUnits>::BYTES;
 }
 
-template <class Tag, int D, int F, typename GT>
-hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
-    const GT* d_out = (const GT*)c.d_out;
-    constexpr int V = Tag::simplex ? D + 1 : (1 << D);
-    constexpr bool kNetOk = F == 2 && D <= 3;
-    const bool net = c.net.x != nullptr;
-    const double N = (double)c.N, gs = sizeof(GT), rec = sizeof(BinRec<F>);
-    const double counts = (double)p.W * p.B * 4.0;
-    (void)rec;
-    // the method's scatter payload: one binary32 value per point, level,
-    // vertex and feature (however many records carry it)
-    const double payload = N * (p.l1 - p.l0) * V * F * 4.0;
-    // The staged scatter (when its LDS fits) merges runs of one slot across
-    // lanes, and its count pass counts the merged records the same way, in
-    // the same shape (few buckets per level or many).
-    const bool few = p.bmax <= kStageFewBuckets && V >= 4;
-    bool staged = false;
-    size_t staged_lds = 0;
-    if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
-        staged_lds = staged_lds_bytes<V, F>(p.B, p.bmax, few);
-        staged = staged_lds <= kStageLdsMax;
+// Shape of a group's count pass and scatter: the staged scatter (when its
+// LDS fits) merges runs of one slot across lanes, and its count pass counts
+// the merged records the same way, in the same shape (few buckets per level
+// or many).
+template <int V, int F>
+struct ScatterShape {
+    bool few, staged;
+    size_t staged_lds;
+    explicit ScatterShape(const BinPlan& p) : few(p.bmax <= kStageFewBuckets && V >= 4), staged(false), staged_lds(0) {
+        if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
+            staged_lds = staged_lds_bytes<V, F>(p.B, p.bmax, few);
+            staged = staged_lds <= kStageLdsMax;
+        }
     }
-    if (net && (!kNetOk || !staged || net_lds_bytes<V, F>(p.B, p.bmax) > kNetLdsMax))
-        return hipErrorNotSupported;  // checked by the caller before any launch
+};
+
+// The part of a group's adjoint that depends only on the points: records
+// counted per (workgroup, bucket), the column scan and the scan of the
+// bucket totals, which lay out every record's place in the workspace.
+template <class Tag, int D, int F>
+hipError_t bin_prepare_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals) {
+    constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+    const ScatterShape<V, F> sh(p);
+    const double N = (double)c.N, counts = (double)p.W * p.B * 4.0;
     trace_begin(c.stream, "bin_count", N * 4.0 * D + counts);
     // Without a densely stored level the staged kernels never compute dense
     // rows (they are bound by vector instructions where runs are merged).
     const bool dense = c.lv.dense != 0;
-    if (staged) {
+    const bool few = sh.few;
+    if (sh.staged) {
         if constexpr (stage_ppt<V, false>() >= 1 && stage_ppt<V, true>() >= 1) {
             const size_t lds = p.B * sizeof(uint32_t);
             if (few && dense)
@@ -778,6 +779,32 @@ hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t*
     trace_begin(c.stream, "bin_scan", 8.0 * p.B + 4.0);
     bin_scan_kernel<<<1, 1024, 0, c.stream>>>(p.B, totals, p.base);
     trace_end(c.stream);
+    return hipGetLastError();
+}
+
+// One level group of the adjoint; `prepared`: its count and scans were run
+// by a preceding prepare call on the same points and workspace.
+template <class Tag, int D, int F, typename GT>
+hipError_t binned_adjoint_group(const EncodeCall& c, const BinPlan& p, uint32_t* totals, bool prepared) {
+    const GT* d_out = (const GT*)c.d_out;
+    constexpr int V = Tag::simplex ? D + 1 : (1 << D);
+    constexpr bool kNetOk = F == 2 && D <= 3;
+    const bool net = c.net.x != nullptr;
+    const double N = (double)c.N, gs = sizeof(GT);
+    const double counts = (double)p.W * p.B * 4.0;
+    // the method's scatter payload: one binary32 value per point, level,
+    // vertex and feature (however many records carry it)
+    const double payload = N * (p.l1 - p.l0) * V * F * 4.0;
+    const ScatterShape<V, F> sh(p);
+    const bool few = sh.few, staged = sh.staged;
+    const size_t staged_lds = sh.staged_lds;
+    if (net && (!kNetOk || !staged || net_lds_bytes<V, F>(p.B, p.bmax) > kNetLdsMax))
+        return hipErrorNotSupported;  // checked by the caller before any launch
+    if (!prepared) {
+        const hipError_t e = bin_prepare_group<Tag, D, F>(c, p, totals);
+        if (e != hipSuccess) return e;
+    }
+    const bool dense = c.lv.dense != 0;
     // The privatised coarse levels depend only on the points and the output
     // gradient, and their sums are needed only by the accumulation: they run
     // on a side stream beside the scatter (LDS-atomic bound beside store
@@ -872,11 +899,17 @@ hipError_t binned_adjoint(const EncodeCall& c) {
         }
         if (c.net.check_only) return hipSuccess;
     }
+    if (c.op == EncodeOp::AdjointPrepare) {
+        if (!lay.ok || c.net.x) return hipErrorInvalidValue;
+        BinPlan p = bin_plan(lay, 0, ws);
+        return bin_prepare_group<Tag, D, F>(c, p, (uint32_t*)(ws + lay.off_totals));
+    }
     for (int g = 0; g < lay.groups; ++g) {
         BinPlan p = bin_plan(lay, g, ws);
         uint32_t* totals = (uint32_t*)(ws + lay.off_totals);
-        hipError_t e = c.dout_f16 ? binned_adjoint_group<Tag, D, F, f16>(c, p, totals)
-                                  : binned_adjoint_group<Tag, D, F, float>(c, p, totals);
+        const bool prepared = c.prepared && g == 0;
+        hipError_t e = c.dout_f16 ? binned_adjoint_group<Tag, D, F, f16>(c, p, totals, prepared)
+                                  : binned_adjoint_group<Tag, D, F, float>(c, p, totals, prepared);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

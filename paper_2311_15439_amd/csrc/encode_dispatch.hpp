@@ -83,7 +83,8 @@ hipError_t input_grad_dispatch_types(const EncodeCall& c) {
 template <class Tag, int D, int F>
 hipError_t dispatch_op(const EncodeCall& c) {
     switch (c.op) {
-        case EncodeOp::AdjointBinned: return binned_adjoint<Tag, D, F>(c);
+        case EncodeOp::AdjointBinned:
+        case EncodeOp::AdjointPrepare: return binned_adjoint<Tag, D, F>(c);
         case EncodeOp::InputGrad: return input_grad_dispatch_types<Tag, D, F>(c);
         case EncodeOp::Forward: return fwd_dispatch_types<Tag, D, F>(c);
         case EncodeOp::Adjoint: return bwd_dispatch_types<Tag, D, F>(c);

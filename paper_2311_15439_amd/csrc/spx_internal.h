@@ -122,7 +122,10 @@ struct AdamArgs {
     float lr, b1, b2, eps, inv_bc1, inv_bc2;
 };
 
-enum class EncodeOp { Forward, Adjoint, AdjointBinned, Debug, Twin, InputGrad };
+// AdjointPrepare: the binned adjoint's first level group counted and laid
+// out in the workspace (it depends only on the points), for a following
+// AdjointBinned call with `prepared` set.
+enum class EncodeOp { Forward, Adjoint, AdjointBinned, AdjointPrepare, Debug, Twin, InputGrad };
 
 // Binned adjoint: one level group's plan (device pointers into the caller's
 // workspace).  Levels [0, P) of group 0 are privatised: their contributions
@@ -359,6 +362,7 @@ struct EncodeCall {
     uint32_t* idx;
     float* w;
     void* workspace;  // binned adjoint only
+    bool prepared;    // binned adjoint only: group 0 counted by a preceding AdjointPrepare call
     AdamArgs adam;    // binned adjoint only
     // binned adjoint only: when net.x is set, the output gradient is the
     // network's input gradient, computed in the scatter from the features

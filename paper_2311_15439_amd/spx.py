@@ -72,6 +72,10 @@ _SIGNATURES = {
     "spx_encode_bwd_workspace": (C.c_int, [_P, C.c_int64, _P]),
     "spx_encode_bwd_adam": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_float, C.c_float,
                                       C.c_float, C.c_float, C.c_int64, _P, C.c_size_t, _P]),
+    "spx_encode_bwd_prepare": (C.c_int, [_P, C.c_int64, _P, _P, C.c_size_t, _P]),
+    "spx_encode_bwd_prepared": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P, C.c_size_t, _P]),
+    "spx_encode_bwd_adam_prepared": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_float,
+                                               C.c_float, C.c_float, C.c_float, C.c_int64, _P, C.c_size_t, _P]),
     "spx_encode_debug": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_encode_gather_twin": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
     "spx_gather_probe": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_uint32, _P, _P]),
@@ -273,7 +277,25 @@ def spx_encode_bwd_workspace(enc: Encoding, N: int) -> int:
     return int(out.value)
 
 
-def spx_encode_bwd(enc: Encoding, pts, d_out, d_tables, workspace=None, stream=None) -> None:
+def spx_encode_bwd_prepare(enc: Encoding, pts, workspace, stream=None) -> None:
+    """The adjoint's counting pass (points only) into ``workspace``, for a
+    following spx_encode_bwd_prepared / spx_encode_bwd_adam_prepared call on
+    the same points and workspace (the caller orders the two streams)."""
+    torch = _torch()
+    N = pts.shape[0]
+    if pts.shape != (N, enc.n_dims):
+        raise ValueError("pts shape does not match the encoding")
+    _check(lib().spx_encode_bwd_prepare(enc.ref(), N, _dev(pts, torch.float32, "pts"),
+                                        _dev(workspace, torch.uint8, "workspace"), workspace.numel(),
+                                        _stream(stream)), "spx_encode_bwd_prepare")
+
+
+def spx_encode_bwd_prepared(enc: Encoding, pts, d_out, d_tables, workspace, stream=None) -> None:
+    """spx_encode_bwd (binned) after spx_encode_bwd_prepare."""
+    spx_encode_bwd(enc, pts, d_out, d_tables, workspace, stream, _prepared=True)
+
+
+def spx_encode_bwd(enc: Encoding, pts, d_out, d_tables, workspace=None, stream=None, _prepared=False) -> None:
     """Accumulates into d_tables [L, T, F] float32 (caller zeroes it).  With a
     uint8 GPU ``workspace`` of spx_encode_bwd_workspace() bytes the binned
     path runs; without one, the atomic path."""
@@ -285,13 +307,21 @@ def spx_encode_bwd(enc: Encoding, pts, d_out, d_tables, workspace=None, stream=N
         raise ValueError("d_out shape must be [N, L*F]")
     ws = None if workspace is None else _dev(workspace, torch.uint8, "workspace")
     nbytes = 0 if workspace is None else workspace.numel()
-    _check(lib().spx_encode_bwd(enc.ref(), N, _dev(pts, torch.float32, "pts"), _dev(d_out, None, "d_out"),
+    name = "spx_encode_bwd_prepared" if _prepared else "spx_encode_bwd"
+    _check(getattr(lib(), name)(enc.ref(), N, _dev(pts, torch.float32, "pts"), _dev(d_out, None, "d_out"),
                                 _dtype_code(d_out), _dev(d_tables, torch.float32, "d_tables"), ws, nbytes,
-                                _stream(stream)), "spx_encode_bwd")
+                                _stream(stream)), name)
+
+
+def spx_encode_bwd_adam_prepared(enc: Encoding, pts, d_out, param, m, v, param_f16=None, *, lr, beta1=0.9,
+                                 beta2=0.99, eps=1e-15, step, workspace, stream=None) -> None:
+    """spx_encode_bwd_adam after spx_encode_bwd_prepare."""
+    spx_encode_bwd_adam(enc, pts, d_out, param, m, v, param_f16, lr=lr, beta1=beta1, beta2=beta2, eps=eps,
+                        step=step, workspace=workspace, stream=stream, _prepared=True)
 
 
 def spx_encode_bwd_adam(enc: Encoding, pts, d_out, param, m, v, param_f16=None, *, lr, beta1=0.9, beta2=0.99,
-                        eps=1e-15, step, workspace, stream=None) -> None:
+                        eps=1e-15, step, workspace, stream=None, _prepared=False) -> None:
     """Adjoint + Adam on the tables in one pass (no gradient table)."""
     torch = _torch()
     N = pts.shape[0]
@@ -301,12 +331,13 @@ def spx_encode_bwd_adam(enc: Encoding, pts, d_out, param, m, v, param_f16=None, 
     if tuple(d_out.shape) != (N, enc.n_levels * enc.n_feat):
         raise ValueError("d_out shape must be [N, L*F]")
     f = torch.float32
-    _check(lib().spx_encode_bwd_adam(enc.ref(), N, _dev(pts, f, "pts"), _dev(d_out, None, "d_out"), _dtype_code(d_out),
-                                     _dev(param, f, "param"), _dev(m, f, "m"), _dev(v, f, "v"),
-                                     None if param_f16 is None else _dev(param_f16, torch.float16, "param_f16"),
-                                     float(lr), float(beta1), float(beta2), float(eps), int(step),
-                                     _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)),
-           "spx_encode_bwd_adam")
+    name = "spx_encode_bwd_adam_prepared" if _prepared else "spx_encode_bwd_adam"
+    _check(getattr(lib(), name)(enc.ref(), N, _dev(pts, f, "pts"), _dev(d_out, None, "d_out"), _dtype_code(d_out),
+                                _dev(param, f, "param"), _dev(m, f, "m"), _dev(v, f, "v"),
+                                None if param_f16 is None else _dev(param_f16, torch.float16, "param_f16"),
+                                float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)),
+           name)
 
 
 def spx_encode_debug(enc: Encoding, pts, idx=None, w=None, stream=None) -> None:

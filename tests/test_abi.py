@@ -128,6 +128,21 @@ def test_encode_argument_checks_on_host():
     assert L.spx_encode_bwd(good.ref(), 5, fake, fake, spx.SPX_F32, fake, C.c_void_p(0x10010), need, s) \
         == spx.SPX_EALIGN
     assert L.spx_encode_debug(good.ref(), 5, fake, None, None, s) == spx.SPX_OK  # nothing requested
+    # the adjoint split in two: the counting pass and the adjoints after it need the workspace
+    ws = C.c_void_p(0x100000)
+    assert L.spx_encode_bwd_prepare(good.ref(), 0, None, None, 0, s) == spx.SPX_OK
+    assert L.spx_encode_bwd_prepare(good.ref(), -1, fake, ws, need, s) == spx.SPX_EINVAL
+    assert L.spx_encode_bwd_prepare(good.ref(), 5, None, ws, need, s) == spx.SPX_EINVAL
+    assert L.spx_encode_bwd_prepare(good.ref(), 5, fake, None, need, s) == spx.SPX_EINVAL
+    assert L.spx_encode_bwd_prepare(good.ref(), 5, fake, ws, need - 1, s) == spx.SPX_EINVAL
+    assert L.spx_encode_bwd_prepare(good.ref(), 5, fake, C.c_void_p(0x100010), need, s) == spx.SPX_EALIGN
+    assert L.spx_encode_bwd_prepared(good.ref(), 5, fake, fake, spx.SPX_F32, fake, None, 0, s) == spx.SPX_EINVAL
+    assert L.spx_encode_bwd_prepared(good.ref(), 5, fake, fake, spx.SPX_F32, fake, ws, need - 1, s) == spx.SPX_EINVAL
+    adam = (C.c_float(1e-2), C.c_float(0.9), C.c_float(0.99), C.c_float(1e-15))
+    assert L.spx_encode_bwd_adam_prepared(good.ref(), 5, fake, fake, spx.SPX_F32, ws, ws, ws, None, *adam, 1,
+                                          None, 0, s) == spx.SPX_EINVAL
+    assert L.spx_encode_bwd_adam_prepared(good.ref(), 5, fake, fake, spx.SPX_F32, ws, ws, ws, None, *adam, 0,
+                                          ws, need, s) == spx.SPX_EINVAL  # step < 1
 
 
 def test_other_argument_checks_on_host():
