@@ -263,6 +263,8 @@ class TrainStep:
         if self.prepare:
             self.side = torch.cuda.Stream()  # default priority
             self.ev_fork, self.ev_join = torch.cuda.Event(), torch.cuda.Event()
+            # the network's Adam step also runs there, beside the adjoint
+            self.ev_mlp, self.ev_adam = torch.cuda.Event(), torch.cuda.Event()
         if self.fused_bwd:
             self.nws = torch.empty(spx.spx_encode_mlp_bwd_workspace(self.enc, self.mlp, self.N), dtype=torch.uint8,
                                    device=dev)
@@ -317,9 +319,25 @@ class TrainStep:
             calls.append(("adam_tables", lambda: spx.spx_adam_step(
                 self.master, self.grad, self.m, self.v, self.tab16, lr=self.lr, beta1=0.9, beta2=0.99, eps=1e-15,
                 step=self.t, zero_grad=True)))
-        calls.append(("adam_mlp", lambda: spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=self.lr,
-                                                            beta1=0.9, beta2=0.99, eps=1e-15, step=self.t,
-                                                            zero_grad=False)))
+        def adam_mlp(stream=None):
+            spx.spx_adam_step(self.Wm, self.dW, self.Wmm, self.Wvv, self.W16, lr=self.lr, beta1=0.9, beta2=0.99,
+                              eps=1e-15, step=self.t, zero_grad=False, stream=stream)
+        if self.prepare:
+            # the network's Adam step on the side stream as soon as its
+            # gradient is reduced, beside the adjoint; the caller's stream
+            # waits for it at the end of the step (the next forward reads
+            # the weights)
+            def adam_side():
+                import torch
+                self.ev_mlp.record(torch.cuda.current_stream())
+                self.side.wait_event(self.ev_mlp)
+                adam_mlp(self.side)
+                self.ev_adam.record(self.side)
+            k = next(i for i, (nm, _) in enumerate(calls) if nm == "mlp_bwd") + 1
+            calls.insert(k, ("adam_mlp", adam_side))
+            calls.append(("join", lambda: self.torch.cuda.current_stream().wait_event(self.ev_adam)))
+        else:
+            calls.append(("adam_mlp", adam_mlp))
         return calls
 
     def _loss_calls(self, b, tgt):
@@ -363,6 +381,7 @@ class TrainStep:
             "encode_mlp_bwd_adam": N * (4 * n + 2 * D + 4 * self.d_out + L * V * F * 8) + P * 26,
             "adam_tables": P * 34 if not self.fused else 0,
             "adam_mlp": nw * 34,
+            "join": 0,
         }
 
 
