@@ -204,6 +204,22 @@ def _colour_target(w):
     return w.name.startswith("image") or w.name.startswith("field")
 
 
+_SIDE_STREAM = None
+
+
+def side_stream():
+    """The one second stream (default priority) every step and timing here
+    uses beside the caller's stream.  Streams share the device's few hardware
+    queues round-robin, so a stream created later may land on the same queue
+    as the caller's stream and run serialised behind it; reusing the first
+    one keeps the two apart for the whole run."""
+    global _SIDE_STREAM
+    if _SIDE_STREAM is None:
+        import torch
+        _SIDE_STREAM = torch.cuda.Stream()
+    return _SIDE_STREAM
+
+
 class TrainStep:
     """All device buffers of one training step; launches only library kernels."""
 
@@ -261,7 +277,7 @@ class TrainStep:
         # before the adjoint (spx_encode_bwd_prepare, then the *_prepared call)
         self.prepare = fused and not self.fused_bwd
         if self.prepare:
-            self.side = torch.cuda.Stream()  # default priority
+            self.side = side_stream()
             self.ev_fork, self.ev_join = torch.cuda.Event(), torch.cuda.Event()
             # the network's Adam step also runs there, beside the adjoint
             self.ev_mlp, self.ev_adam = torch.cuda.Event(), torch.cuda.Event()
@@ -666,7 +682,7 @@ def time_encode_sweep(reps=30, warm=5, probe=None):
             torch.cuda.synchronize()
             # forward + adjoint with the adjoint's counting pass (points only) on
             # a second stream beside the forward, joined before the adjoint
-            side = torch.cuda.Stream()  # default priority
+            side = side_stream()
             pev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
             fork = [torch.cuda.Event() for _ in range(reps)]
             join = [torch.cuda.Event() for _ in range(reps)]
