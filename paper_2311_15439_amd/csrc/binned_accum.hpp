@@ -128,6 +128,27 @@ __device__ __forceinline__ void add_record_wave(float* acc, bool ok, const BinRe
     lds_add_wave<F>(acc, ok, rec.slot, rec.v);
 }
 
+// U records per thread in flight before their LDS adds; the loop bounds
+// are uniform over the workgroup (lanes past the end idle).  The loads are
+// unconditional (a lane past the end rereads record rb, which exists) so
+// that all of them are issued before the first wait.
+template <int F, int U>
+__device__ __forceinline__ void accum_records(float* acc, const BinRec<F>* __restrict__ recs, uint32_t r0,
+                                              uint32_t r1) {
+    for (uint32_t rb = r0; rb < r1; rb += U * kAccBlock) {
+        BinRec<F> rec[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t r = rb + threadIdx.x + u * kAccBlock;
+            ok[u] = r < r1;
+            rec[u] = recs[ok[u] ? r : rb];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add_record_wave<F>(acc, ok[u], rec[u]);
+    }
+}
+
 constexpr int kAccPre = 8;  // float4 chunks of the slice a thread preloads
 
 template <int D, int F, bool ADAM>
@@ -203,23 +224,13 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
         r1 = r0 + (uint32_t)(n * (uint64_t)(part + 1) / (uint64_t)K);
         r0 = r0 + (uint32_t)(n * (uint64_t)part / (uint64_t)K);
     }
-    // U records per thread in flight before their LDS adds; the loop bounds
-    // are uniform over the workgroup (lanes past the end idle).  The loads
-    // are unconditional (a lane past the end rereads record rb, which
-    // exists) so that all of them are issued before the first wait.
-    constexpr int U = acc_unroll<ADAM>();
-    for (uint32_t rb = r0; rb < r1; rb += U * kAccBlock) {
-        BinRec<F> rec[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t r = rb + threadIdx.x + u * kAccBlock;
-            ok[u] = r < r1;
-            rec[u] = recs[ok[u] ? r : rb];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) add_record_wave<F>(acc, ok[u], rec[u]);
-    }
+    // A bucket of many records (64 or more per thread: the volume
+    // workload's fine levels) is bound by its record phase; there two
+    // records per thread are in flight even beside the preloaded state.
+    if (ADAM && r1 - r0 >= 64u * kAccBlock)
+        accum_records<F, 2>(acc, recs, r0, r1);
+    else
+        accum_records<F, acc_unroll<ADAM>()>(acc, recs, r0, r1);
     __syncthreads();
     if (K > 1) {  // a part of a split bucket: its sums go to its partial slice
         float* __restrict__ dst = plan.split + (size_t)(plan.soff[l] + (int64_t)slice * K + part) * ((size_t)F << plan.s_log2);
