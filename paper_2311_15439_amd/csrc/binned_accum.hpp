@@ -225,10 +225,11 @@ __global__ __launch_bounds__(kAccBlock) void bin_accum_kernel(BinPlan plan, Leve
         r0 = r0 + (uint32_t)(n * (uint64_t)part / (uint64_t)K);
     }
     // A bucket of many records (64 or more per thread: the volume
-    // workload's fine levels) is bound by its record phase; there two
-    // records per thread are in flight even beside the preloaded state.
+    // workload's fine levels) is bound by its record phase; there four
+    // records per thread are in flight even beside the preloaded state
+    // (128 registers, no spill).
     if (ADAM && r1 - r0 >= 64u * kAccBlock)
-        accum_records<F, 2>(acc, recs, r0, r1);
+        accum_records<F, 4>(acc, recs, r0, r1);
     else
         accum_records<F, acc_unroll<ADAM>()>(acc, recs, r0, r1);
     __syncthreads();
